@@ -42,7 +42,9 @@ def test_invariants_through_stages_4x4():
     o = OracleREWL(4, 1, (3, 4), 1, 16, (4, 5), 10_000, seed=0)
     o.init()
     trials = [0]
-    while not o.info()["done"] and len(trials) < 8:
+    for _ in range(400):
+        if o.info()["done"] or len(trials) >= 8:
+            break
         s_before = o.info()["stage"]
         o.sweep(o.X)
         trials[s_before] += o.X
@@ -51,6 +53,27 @@ def test_invariants_through_stages_4x4():
         if o.info()["stage"] != s_before:
             trials.append(0)
     assert len(trials) >= 4
+
+
+def test_update_lands_on_the_state_after_the_decision():
+    # Sec. 2: on accept g and H change at the trial state, on reject at the
+    # current one -- either way at the state the walker holds afterwards, so
+    # after every trial the walker's bin has been counted in this stage.
+    for L, nw, W in ((4, 1, 1), (8, 3, 2)):
+        o = OracleREWL(L, nw, (3, 4), W, 16, (4, 5), 10_000, seed=3)
+        o.init()
+        moved = 0
+        prev = None
+        for _ in range(400):
+            o.sweep(1)
+            for g in range(o.n_walkers):
+                d = o.walker(g)
+                i = (d["e"] - d["lo"], d["m"])
+                assert d["H"][i] > 0 and d["lng"][i] > 0
+            cur = [(o.walker(g, False)["e"], o.walker(g, False)["m"]) for g in range(o.n_walkers)]
+            moved += prev is not None and cur != prev
+            prev = cur
+        assert moved > 50
 
 
 def test_invariants_rewl_16x16_prefix():

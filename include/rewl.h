@@ -1,0 +1,174 @@
+/*
+ * rewl.h -- C ABI of the MI355X (gfx950) implementation of two-dimensional
+ * replica-exchange Wang-Landau sampling (2D-REWL) of the periodic L x L Ising
+ * model, after Valentim et al., arXiv:1508.02748.
+ *
+ * The calls follow the paper's problem statement (Sec. 2): split the energy
+ * range into overlapping windows with the full magnetization range, run
+ * Wang-Landau walkers in each window (Eq. 1), check flatness and refine ln f,
+ * exchange configurations between adjacent windows (Eq. 2), and finally join
+ * the per-walker ln g(E,M) pieces (Eq. 3, Eq. 4).  A second family of calls
+ * reweights a joint DOS into ln Z(beta, h) and its derivatives.
+ *
+ * Conventions shared by every call
+ *   - Every call returns rewl_status (0 = OK, < 0 = error); rewl_last_error()
+ *     gives a message for the calling thread's most recent error.
+ *   - Energy bins e = (E + 2N)/4 in [0, N], magnetization bins m = (M + N)/2
+ *     in [0, N] (m = number of up spins); N = L*L, E = -sum_<ij> s_i s_j.
+ *   - ln g is int64 fixed point in units of 2^-k_final; ln f at stage s is
+ *     2^-s, i.e. 2^(k_final - s) units.  H is the visit count of the current
+ *     stage.
+ *   - Device memory is owned by the caller: rewl_plan_buffer_sizes() says how
+ *     many bytes each buffer needs and rewl_plan_bind() lends the library
+ *     device pointers (any allocator; the Python binding uses PyTorch) and a
+ *     hipStream_t.  The library never frees them; they must outlive the plan.
+ *   - All device work is enqueued on the bound stream.  Only rewl_init,
+ *     rewl_query, rewl_read_walker and rewl_merge_lng synchronise it.
+ *   - Arguments are validated before any device work (REWL_EINVAL).  A HIP
+ *     error surfaces as REWL_EDEVICE; after it the plan answers REWL_ESTATE
+ *     to every call but rewl_plan_destroy.
+ *   - Results are deterministic: with the same problems and seeds every call
+ *     sequence gives bit-identical spins, E, M, ln g and H, whatever the
+ *     tuning or form (batched / plain), because every random number is a
+ *     Philox4x32-10 draw addressed by (seed, walker, attempt index).
+ */
+#ifndef REWL_H
+#define REWL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    REWL_OK = 0,
+    REWL_EINVAL = -1,     /* bad argument, nothing was done */
+    REWL_ENOMEM = -2,     /* host allocation failed */
+    REWL_EDEVICE = -3,    /* a HIP call or kernel failed */
+    REWL_ESTATE = -4,     /* plan not bound / in error / entry walk exceeded its cap */
+    REWL_EOVERFLOW = -5,  /* ln g would leave int64 headroom */
+    REWL_ENOTREADY = -6   /* reserved */
+} rewl_status;
+
+/* One REWL simulation -- the paper's problem statement (Sec. 2, Sec. 3). */
+typedef struct {
+    int32_t L;                   /* even, 4..64: periodic L x L, J = 1, h = 0 while sampling */
+    int32_t n_windows;           /* >= 1 energy windows, full M range each (Sec. 3) */
+    int32_t overlap_num;         /* overlap of neighbouring windows = num/den, */
+    int32_t overlap_den;         /*   e.g. 3/4, or 1/2 as in the paper's runs */
+    int32_t walkers_per_window;  /* >= 1, independent g and H each (Sec. 2); <= 256 */
+    int32_t k_final;             /* ln f runs 2^0 .. 2^-k_final; 0 <= k_final <= 40 */
+    int32_t flat_num;            /* flat iff min H >= num/den * mean H over */
+    int32_t flat_den;            /*   visited bins; 4/5 = the paper's 80 % */
+    int64_t interval;            /* trials per walker between flatness checks and
+                                    exchange rounds; >= 1 */
+    uint64_t seed;               /* Philox key */
+    int32_t init;                /* 0: spins Bernoulli(1/2) from Philox; 1: all +1 */
+    int32_t reserved;            /* must be 0 */
+} rewl_problem;
+
+/* Execution form and tuning.  None of these change results. */
+enum { REWL_FORM_BATCHED = 0, REWL_FORM_PLAIN = 1 };
+typedef struct {
+    int32_t form;             /* REWL_FORM_BATCHED: all problems, windows and walkers
+                                 in one launch per interval, device-side stage
+                                 control, intervals replayed from a HIP graph;
+                                 REWL_FORM_PLAIN: one launch per window and a host
+                                 round trip per interval */
+    int32_t walkers_per_wg;   /* 64, 128 or 256 lanes (= walkers) per workgroup; 0 = auto */
+    int32_t graph_intervals;  /* intervals captured per graph (batched); 0 = auto */
+    int32_t grid_waves_per_cu;/* persistent grid size in waves per CU; 0 = one tile per workgroup */
+    int32_t reserved[4];      /* must be 0 */
+} rewl_tuning;
+
+/* Buffers the caller provides (device memory). */
+enum {
+    REWL_BUF_TABLES = 0,  /* ln g / H tables: 16 B per (walker, e in window, m) bin */
+    REWL_BUF_SPINS = 1,   /* bit-packed configurations */
+    REWL_BUF_STATE = 2,   /* descriptors, walker and problem state, scratch */
+    REWL_NBUF = 3
+};
+
+typedef struct rewl_plan rewl_plan;
+
+/* Validate problems, compute windows (Sec. 2, Fig. 1(b)) and buffer sizes.
+ * `tuning` may be NULL (batched form, automatic choices).  n_problems >= 1. */
+rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems,
+                             const rewl_tuning* tuning, rewl_plan** out);
+void rewl_plan_destroy(rewl_plan* plan);
+
+/* Bytes per buffer (sizes_out has REWL_NBUF entries). */
+rewl_status rewl_plan_buffer_sizes(const rewl_plan* plan, size_t* sizes_out);
+
+/* Lend device buffers (REWL_NBUF pointers, 256-byte aligned, at least the
+ * sizes above) and the hipStream_t to enqueue on (NULL = default stream). */
+rewl_status rewl_plan_bind(rewl_plan* plan, void* const* dev_ptrs, void* hip_stream);
+
+/* Energy-bin bounds [E_lo, E_hi] of window w of problem prob. */
+rewl_status rewl_window_bounds(const rewl_plan* plan, int32_t prob, int32_t w,
+                               int32_t* e_lo, int32_t* e_hi);
+
+/* Counts of the plan: problems, walkers in total. */
+rewl_status rewl_plan_counts(const rewl_plan* plan, int32_t* n_problems, int64_t* n_walkers);
+
+/* Initial configurations and entry of every walker into its window
+ * (Metropolis at unit temperature on the distance to the window); zeroes all
+ * tables.  Synchronises.  REWL_ESTATE if a walker needs more than 2^40 entry
+ * trials. */
+rewl_status rewl_init(rewl_plan* plan);
+
+/* n_intervals x { interval trials per walker (Eq. 1 walk), flatness check and
+ * ln f reduction, exchange round (Eq. 2) }.  Problems that have finished stop
+ * changing.  Enqueued (the plain form synchronises once per interval). */
+rewl_status rewl_run(rewl_plan* plan, int64_t n_intervals);
+
+/* The three parts of an interval, separately: n trials per walker of every
+ * unfinished problem; the flatness check and stage advance ("reduce ln f");
+ * the exchange round of the boundary last closed by rewl_reduce_lnf. */
+rewl_status rewl_sweep(rewl_plan* plan, int64_t n_trials);
+rewl_status rewl_reduce_lnf(rewl_plan* plan);
+rewl_status rewl_exchange(rewl_plan* plan);
+
+/* Per problem: stage s, done flag, trials made per walker.  Arrays of
+ * n_problems entries; any may be NULL.  Synchronises. */
+rewl_status rewl_query(rewl_plan* plan, int32_t* stage_out, int32_t* done_out,
+                       int64_t* trials_out);
+
+/* State of walker a of window w of problem prob.  lng and H (nullable) get the
+ * window table, (E_hi - E_lo + 1) x (N + 1) row-major by (e - E_lo, m), with
+ * cap_bins entries of room; spins (nullable) gets N bytes +1/-1 in row-major
+ * site order; e, m, t (nullable) the current bins and trial count.
+ * Synchronises. */
+rewl_status rewl_read_walker(rewl_plan* plan, int32_t prob, int32_t w, int32_t a,
+                             int64_t* lng, uint64_t* H, size_t cap_bins, int8_t* spins,
+                             int32_t* e, int32_t* m, int64_t* t);
+
+/* Reweighting of a joint DOS (float64 ln g over bins (e, m), -inf = not
+ * visited) into ln Z(beta, h) = log sum exp(ln g - beta E + beta h M) at G
+ * grid points; all pointers are device pointers.  lng is nE x nM row-major for
+ * e = e0 .. e0+nE-1, m = m0 .. m0+nM-1 of a lattice of N spins.  beta, h, lnz
+ * have G entries. */
+rewl_status rewl_lnz_forward(const double* lng, int32_t N, int32_t e0, int32_t nE,
+                             int32_t m0, int32_t nM, const double* beta, const double* h,
+                             int64_t G, double* lnz, void* hip_stream);
+
+/* Backward of rewl_lnz_forward.  order 1: with the saved lnz and upstream
+ * grad_out, writes grad_beta = g <-E + hM>, grad_h = g beta <M> (each G
+ * entries) and, if grad_lng is not NULL, grad_lng = sum_g g p_g(E,M)
+ * (nE x nM).  order 2: writes, per grid point, the first moments and the
+ * covariances needed for second derivatives into mom (G x 5 doubles:
+ * <M>, <U>, Var(U), Var(M), Cov(U,M), U = -E + hM); grad pointers unused. */
+rewl_status rewl_lnz_backward(const double* lng, int32_t N, int32_t e0, int32_t nE,
+                              int32_t m0, int32_t nM, const double* beta, const double* h,
+                              int64_t G, const double* lnz, const double* grad_out,
+                              double* grad_beta, double* grad_h, double* grad_lng,
+                              double* mom, int32_t order, void* hip_stream);
+
+const char* rewl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* REWL_H */

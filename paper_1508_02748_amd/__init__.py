@@ -1,0 +1,320 @@
+"""MI355X (gfx950) two-dimensional replica-exchange Wang-Landau sampling.
+
+A thin binding of the C ABI in ``include/rewl.h`` (``librewl.so``): argument
+marshalling only.  Every step of the sampling and of the reweighting runs in the
+library's HIP kernels; PyTorch provides device memory and the stream.  The
+library must have been built (``python -m paper_1508_02748_amd.build``); there
+is no fallback.
+
+Method: Valentim et al., "Exploring Replica-Exchange Wang-Landau sampling in
+higher-dimensional parameter space" (arXiv:1508.02748), Sec. 2: joint density
+of states g(E, M) of the periodic L x L Ising model from Wang-Landau walkers in
+overlapping energy windows with configuration exchange (Eq. 1, Eq. 2).
+"""
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librewl.so")
+
+REWL_OK, REWL_EINVAL, REWL_ENOMEM, REWL_EDEVICE, REWL_ESTATE, REWL_EOVERFLOW, REWL_ENOTREADY = \
+    0, -1, -2, -3, -4, -5, -6
+FORM_BATCHED, FORM_PLAIN = 0, 1
+NBUF = 3
+
+
+class RewlError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"rewl status {status}: {message}")
+        self.status = status
+
+
+class _Problem(C.Structure):
+    _fields_ = [("L", C.c_int32), ("n_windows", C.c_int32), ("overlap_num", C.c_int32),
+                ("overlap_den", C.c_int32), ("walkers_per_window", C.c_int32), ("k_final", C.c_int32),
+                ("flat_num", C.c_int32), ("flat_den", C.c_int32), ("interval", C.c_int64),
+                ("seed", C.c_uint64), ("init", C.c_int32), ("reserved", C.c_int32)]
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("form", C.c_int32), ("walkers_per_wg", C.c_int32), ("graph_intervals", C.c_int32),
+                ("grid_waves_per_cu", C.c_int32), ("reserved", C.c_int32 * 4)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librewl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1508_02748_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        sig = {
+            "rewl_plan_create": ([C.POINTER(_Problem), C.c_int32, C.POINTER(_Tuning), C.POINTER(P)], C.c_int),
+            "rewl_plan_destroy": ([P], None),
+            "rewl_plan_buffer_sizes": ([P, C.POINTER(C.c_size_t)], C.c_int),
+            "rewl_plan_bind": ([P, C.POINTER(P), P], C.c_int),
+            "rewl_window_bounds": ([P, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+            "rewl_plan_counts": ([P, C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int),
+            "rewl_init": ([P], C.c_int),
+            "rewl_run": ([P, C.c_int64], C.c_int),
+            "rewl_sweep": ([P, C.c_int64], C.c_int),
+            "rewl_reduce_lnf": ([P], C.c_int),
+            "rewl_exchange": ([P], C.c_int),
+            "rewl_query": ([P, P, P, P], C.c_int),
+            "rewl_read_walker": ([P, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_size_t, P,
+                                  C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int),
+            "rewl_lnz_forward": ([P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_int64,
+                                  P, P], C.c_int),
+            "rewl_lnz_backward": ([P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_int64,
+                                   P, P, P, P, P, P, C.c_int32, P], C.c_int),
+            "rewl_last_error": ([], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != REWL_OK:
+        raise RewlError(status, lib().rewl_last_error().decode())
+
+
+@dataclass
+class Problem:
+    """One REWL simulation (Sec. 2 of the paper; defaults: 80 % flatness)."""
+    L: int
+    n_windows: int = 1
+    overlap: tuple = (3, 4)
+    walkers_per_window: int = 1
+    k_final: int = 20
+    flat: tuple = (4, 5)
+    interval: int = 10_000
+    seed: int = 0
+    init: int = 0
+
+    def _c(self):
+        return _Problem(self.L, self.n_windows, self.overlap[0], self.overlap[1], self.walkers_per_window,
+                        self.k_final, self.flat[0], self.flat[1], self.interval,
+                        self.seed & 0xFFFFFFFFFFFFFFFF, self.init, 0)
+
+    @property
+    def N(self):
+        return self.L * self.L
+
+
+@dataclass
+class Tuning:
+    form: int = FORM_BATCHED
+    walkers_per_wg: int = 0
+    graph_intervals: int = 0
+    grid_waves_per_cu: int = 0
+
+    def _c(self):
+        return _Tuning(self.form, self.walkers_per_wg, self.graph_intervals, self.grid_waves_per_cu,
+                       (C.c_int32 * 4)(0, 0, 0, 0))
+
+
+class Plan:
+    """A batch of REWL problems bound to device buffers allocated by PyTorch."""
+
+    def __init__(self, problems, tuning=None, device="cuda:0", stream=None):
+        import torch
+
+        self.problems = list(problems)
+        arr = (_Problem * len(self.problems))(*[p._c() for p in self.problems])
+        h = C.c_void_p()
+        tn = None if tuning is None else C.byref(tuning._c())
+        _check(lib().rewl_plan_create(arr, len(self.problems), tn, C.byref(h)))
+        self._h = h
+        sizes = (C.c_size_t * NBUF)()
+        _check(lib().rewl_plan_buffer_sizes(h, sizes))
+        self.sizes = list(sizes)
+        self.device = torch.device(device)
+        # uint8 buffers; the caching allocator returns >= 256-byte aligned blocks
+        self.buffers = [torch.empty(max(1, s), dtype=torch.uint8, device=self.device) for s in self.sizes]
+        # a stream of its own (default priority): graph capture is not possible on
+        # the legacy default stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        ptrs = (C.c_void_p * NBUF)(*[b.data_ptr() for b in self.buffers])
+        _check(lib().rewl_plan_bind(h, ptrs, C.c_void_p(self.stream.cuda_stream)))
+        npb = C.c_int32()
+        nw = C.c_int64()
+        _check(lib().rewl_plan_counts(h, C.byref(npb), C.byref(nw)))
+        self.n_problems, self.n_walkers = npb.value, nw.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.rewl_plan_destroy(h)
+            self._h = None
+
+    # ----- the paper's operations
+    def init(self):
+        _check(lib().rewl_init(self._h))
+
+    def run(self, n_intervals):
+        _check(lib().rewl_run(self._h, int(n_intervals)))
+
+    def sweep(self, n_trials):
+        _check(lib().rewl_sweep(self._h, int(n_trials)))
+
+    def reduce_lnf(self):
+        _check(lib().rewl_reduce_lnf(self._h))
+
+    def exchange(self):
+        _check(lib().rewl_exchange(self._h))
+
+    def query(self):
+        n = self.n_problems
+        st = np.zeros(n, np.int32)
+        dn = np.zeros(n, np.int32)
+        tr = np.zeros(n, np.int64)
+        _check(lib().rewl_query(self._h, st.ctypes.data, dn.ctypes.data, tr.ctypes.data))
+        return {"stage": st, "done": dn.astype(bool), "trials": tr}
+
+    def window(self, prob, w):
+        lo, hi = C.c_int32(), C.c_int32()
+        _check(lib().rewl_window_bounds(self._h, prob, w, C.byref(lo), C.byref(hi)))
+        return lo.value, hi.value
+
+    def walker(self, prob, w, a, tables=True):
+        """Walker a of window w of problem prob: lng / H tables (rows e-lo, cols m), spins, e, m, t."""
+        p = self.problems[prob]
+        lo, hi = self.window(prob, w)
+        nb = (hi - lo + 1) * (p.N + 1)
+        lng = np.zeros(nb, np.int64) if tables else None
+        H = np.zeros(nb, np.uint64) if tables else None
+        sp = np.zeros(p.N, np.int8)
+        e, m, t = C.c_int32(), C.c_int32(), C.c_int64()
+        _check(lib().rewl_read_walker(self._h, prob, w, a,
+                                      lng.ctypes.data if tables else None,
+                                      H.ctypes.data if tables else None, nb if tables else 0,
+                                      sp.ctypes.data, C.byref(e), C.byref(m), C.byref(t)))
+        shape = (hi - lo + 1, p.N + 1)
+        return {"lng": None if lng is None else lng.reshape(shape),
+                "H": None if H is None else H.reshape(shape),
+                "spins": sp.reshape(p.L, p.L), "e": e.value, "m": m.value, "t": t.value,
+                "lo": lo, "hi": hi}
+
+
+# ------------------------------------------------------------------ reweighting
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _geom(lng, N, e0, m0):
+    nE, nM = lng.shape
+    return N, e0, nE, m0, nM
+
+
+def lnz_forward(lng, beta, h, N, e0=0, m0=0):
+    """ln Z(beta, h) on the device for a float64 joint ln g table (-inf = unvisited)."""
+    import torch
+    assert lng.dtype == torch.float64 and lng.is_cuda and lng.is_contiguous()
+    beta = beta.contiguous()
+    h = h.contiguous()
+    out = torch.empty_like(beta)
+    st = torch.cuda.current_stream(lng.device).cuda_stream
+    _check(lib().rewl_lnz_forward(_ptr(lng), *_geom(lng, N, e0, m0), _ptr(beta), _ptr(h), beta.numel(),
+                                  _ptr(out), C.c_void_p(st)))
+    return out
+
+
+def lnz_moments(lng, beta, h, lnz, N, e0=0, m0=0):
+    """(G, 5) float64: <M>, <U>, Var(U), Var(M), Cov(U, M) with U = -E + h M."""
+    import torch
+    mom = torch.empty((beta.numel(), 5), dtype=torch.float64, device=lng.device)
+    st = torch.cuda.current_stream(lng.device).cuda_stream
+    _check(lib().rewl_lnz_backward(_ptr(lng), *_geom(lng, N, e0, m0), _ptr(beta.contiguous()),
+                                   _ptr(h.contiguous()), beta.numel(), _ptr(lnz.contiguous()), None, None,
+                                   None, None, _ptr(mom), 2, C.c_void_p(st)))
+    return mom
+
+
+def _lnz_grads(lng, beta, h, lnz, grad_out, N, e0, m0, want_lng):
+    import torch
+    gb = torch.empty_like(beta)
+    gh = torch.empty_like(beta)
+    gl = torch.empty_like(lng) if want_lng else None
+    st = torch.cuda.current_stream(lng.device).cuda_stream
+    _check(lib().rewl_lnz_backward(_ptr(lng), *_geom(lng, N, e0, m0), _ptr(beta), _ptr(h), beta.numel(),
+                                   _ptr(lnz), _ptr(grad_out.contiguous()), _ptr(gb), _ptr(gh), _ptr(gl),
+                                   None, 1, C.c_void_p(st)))
+    return gb, gh, gl
+
+
+def _torch_functions():
+    import torch
+
+    class _LnZBackward(torch.autograd.Function):
+        """(grad_out, beta, h) -> (grad_beta, grad_h) of ln Z, differentiable once more."""
+
+        @staticmethod
+        def forward(ctx, grad_out, beta, h, lng, lnz, N, e0, m0):
+            gb, gh, _ = _lnz_grads(lng, beta, h, lnz, grad_out, N, e0, m0, False)
+            ctx.save_for_backward(grad_out, beta, h, lng, lnz)
+            ctx.geo = (N, e0, m0)
+            return gb, gh
+
+        @staticmethod
+        def backward(ctx, a, b):
+            grad_out, beta, h, lng, lnz = ctx.saved_tensors
+            N, e0, m0 = ctx.geo
+            mom = lnz_moments(lng, beta, h, lnz, N, e0, m0)
+            mM, mU, vU, vM, cUM = mom.unbind(1)
+            a = torch.zeros_like(beta) if a is None else a
+            b = torch.zeros_like(beta) if b is None else b
+            cross = mM + beta * cUM
+            d_go = a * mU + b * beta * mM
+            d_beta = grad_out * (a * vU + b * cross)
+            d_h = grad_out * (a * cross + b * beta * beta * vM)
+            return d_go, d_beta, d_h, None, None, None, None, None
+
+    class LnZ(torch.autograd.Function):
+        """ln Z(beta, h) = logsumexp over (E, M) of ln g - beta E + beta h M.
+
+        Gradients: d/d beta = <-E + h M>, d/d h = beta <M>, d/d ln g = p(E, M);
+        second derivatives (through a second Function) give Var(E - h M),
+        beta^2 Var(M) and the mixed term, i.e. specific heat and susceptibility."""
+
+        @staticmethod
+        def forward(ctx, lng, beta, h, N, e0=0, m0=0):
+            lnz = lnz_forward(lng, beta, h, N, e0, m0)
+            ctx.save_for_backward(lng, beta, h, lnz)
+            ctx.geo = (N, e0, m0)
+            return lnz
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            lng, beta, h, lnz = ctx.saved_tensors
+            N, e0, m0 = ctx.geo
+            g_lng = None
+            if ctx.needs_input_grad[0]:
+                _, _, g_lng = _lnz_grads(lng, beta.detach(), h.detach(), lnz, grad_out.detach(), N, e0, m0, True)
+            gb, gh = _LnZBackward.apply(grad_out, beta, h, lng.detach(), lnz.detach(), N, e0, m0)
+            return g_lng, gb, gh, None, None, None
+
+    return LnZ
+
+
+_LnZ = None
+
+
+def LnZ():
+    """The torch.autograd.Function computing ln Z(beta, h) from a joint ln g."""
+    global _LnZ
+    if _LnZ is None:
+        _LnZ = _torch_functions()
+    return _LnZ

@@ -1,0 +1,637 @@
+// rewl_host.cpp -- the C ABI of include/rewl.h: plan construction, buffer
+// layout, launch sequencing (batched form with graph replay, plain form with
+// one launch per window and a host round trip per interval), read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rewl.h"
+#include "rewl_internal.h"
+
+using namespace rewl;
+
+namespace {
+
+thread_local std::string g_err;
+
+rewl_status fail(rewl_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Overlapping equal-size energy windows over e in [0, N] (Sec. 2, Fig. 1(b)):
+// with overlap p/q and D = q + (n-1)(q-p), window i is
+// [floor(i (q-p) N / D), min(N, ceil((i (q-p) + q) N / D))].
+void window_bounds(int N, int n, int p, int q, int i, int& lo, int& hi) {
+    const long long D = q + static_cast<long long>(n - 1) * (q - p);
+    const long long a = static_cast<long long>(i) * (q - p) * N;
+    const long long b = (static_cast<long long>(i) * (q - p) + q) * N;
+    lo = static_cast<int>(a / D);
+    const long long h = (b + D - 1) / D;
+    hi = static_cast<int>(std::min<long long>(h, N));
+}
+
+}  // namespace
+
+struct rewl_plan {
+    std::vector<rewl_problem> probs;
+    rewl_tuning tune{};
+    std::vector<PDesc> pd;
+    std::vector<WDesc> wd;
+    std::vector<PairDesc> pairs;
+    std::vector<std::vector<int>> lo, hi;  // per problem, per window
+    int64_t n_walk = 0;
+    uint64_t n_bins = 0;
+    uint64_t n_words = 0;
+    int l_max = 0;
+    int64_t interval = 0;
+    size_t sizes[REWL_NBUF] = {0, 0, 0};
+    // STATE buffer offsets
+    size_t off_wd = 0, off_pd = 0, off_pairs = 0, off_e = 0, off_m = 0, off_t = 0, off_te = 0,
+           off_nseen = 0, off_flag = 0, off_scan = 0, off_stage = 0, off_done = 0, off_rnd = 0,
+           off_tstage = 0, off_xr = 0, off_xon = 0, off_lngb = 0, off_tseen = 0, off_cnt = 0;
+    // binding
+    bool bound = false;
+    bool broken = false;
+    bool initialised = false;
+    void* buf[REWL_NBUF] = {nullptr, nullptr, nullptr};
+    hipStream_t stream = nullptr;
+    DevState S{};
+    hipGraphExec_t graph = nullptr;
+    int graph_g = 0;
+};
+
+namespace {
+
+rewl_status dev_fail(rewl_plan* P, hipError_t e, const char* what) {
+    P->broken = true;
+    return fail(REWL_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(P, call, what)                        \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess) return dev_fail(P, e_, what); \
+    } while (0)
+
+rewl_status usable(rewl_plan* P) {
+    if (!P) return fail(REWL_EINVAL, "null plan");
+    if (P->broken) return fail(REWL_ESTATE, "plan is in an error state");
+    if (!P->bound) return fail(REWL_ESTATE, "plan has no device buffers bound");
+    return REWL_OK;
+}
+
+rewl_status validate(const rewl_problem& q, int idx) {
+    auto bad = [&](const char* m) {
+        return fail(REWL_EINVAL, "problem " + std::to_string(idx) + ": " + m);
+    };
+    if (q.L < 4 || q.L > 64 || (q.L & 1)) return bad("L must be even, 4..64");
+    if (q.n_windows < 1) return bad("n_windows must be >= 1");
+    if (q.overlap_den < 1 || q.overlap_num < 0 || q.overlap_num >= q.overlap_den)
+        return bad("overlap must be num/den with 0 <= num < den");
+    if (q.walkers_per_window < 1 || q.walkers_per_window > 256) return bad("walkers_per_window must be 1..256");
+    if (q.k_final < 0 || q.k_final > 40) return bad("k_final must be 0..40");
+    if (q.flat_den < 1 || q.flat_num < 0 || q.flat_num > q.flat_den) return bad("flatness must be num/den <= 1");
+    if (q.interval < 1) return bad("interval must be >= 1");
+    if (q.init != 0 && q.init != 1) return bad("init must be 0 or 1");
+    if (q.reserved != 0) return bad("reserved must be 0");
+    const int N = q.L * q.L;
+    for (int i = 0; i < q.n_windows; ++i) {
+        int lo, hi;
+        window_bounds(N, q.n_windows, q.overlap_num, q.overlap_den, i, lo, hi);
+        if (lo > hi) return bad("too many windows for the energy range");
+    }
+    return REWL_OK;
+}
+
+DevState make_state(rewl_plan* P) {
+    DevState S{};
+    char* st = static_cast<char*>(P->buf[REWL_BUF_STATE]);
+    S.wd = reinterpret_cast<const WDesc*>(st + P->off_wd);
+    S.pd = reinterpret_cast<const PDesc*>(st + P->off_pd);
+    S.pairs = reinterpret_cast<const PairDesc*>(st + P->off_pairs);
+    S.tables = static_cast<Bin*>(P->buf[REWL_BUF_TABLES]);
+    S.spins = static_cast<uint32_t*>(P->buf[REWL_BUF_SPINS]);
+    S.e = reinterpret_cast<int32_t*>(st + P->off_e);
+    S.m = reinterpret_cast<int32_t*>(st + P->off_m);
+    S.t = reinterpret_cast<int64_t*>(st + P->off_t);
+    S.te = reinterpret_cast<int64_t*>(st + P->off_te);
+    S.nseen = reinterpret_cast<uint32_t*>(st + P->off_nseen);
+    S.flag = reinterpret_cast<uint32_t*>(st + P->off_flag);
+    S.scan = reinterpret_cast<uint32_t*>(st + P->off_scan);
+    S.stage = reinterpret_cast<int32_t*>(st + P->off_stage);
+    S.done = reinterpret_cast<int32_t*>(st + P->off_done);
+    S.rnd = reinterpret_cast<int64_t*>(st + P->off_rnd);
+    S.tstage = reinterpret_cast<int64_t*>(st + P->off_tstage);
+    S.xr = reinterpret_cast<int64_t*>(st + P->off_xr);
+    S.xon = reinterpret_cast<int32_t*>(st + P->off_xon);
+    S.lngb = reinterpret_cast<int64_t*>(st + P->off_lngb);
+    S.tseen = reinterpret_cast<int64_t*>(st + P->off_tseen);
+    S.counters = reinterpret_cast<int32_t*>(st + P->off_cnt);
+    S.n_walk = P->n_walk;
+    S.n_prob = static_cast<int32_t>(P->pd.size());
+    S.n_pairs = static_cast<int32_t>(P->pairs.size());
+    return S;
+}
+
+int wg_of(const rewl_plan* P) { return P->tune.walkers_per_wg > 0 ? P->tune.walkers_per_wg : 64; }
+
+rewl_status enqueue_sweep(rewl_plan* P, int64_t n) {
+    HIPCHK(P, launch_sweep(P->S, 0, P->n_walk, n, P->l_max, wg_of(P), P->stream), "sweep launch");
+    return REWL_OK;
+}
+
+rewl_status enqueue_boundary(rewl_plan* P) {
+    HIPCHK(P, launch_flat(P->S, P->stream), "flatness launch");
+    HIPCHK(P, launch_stage(P->S, P->stream), "stage launch");
+    return REWL_OK;
+}
+
+rewl_status enqueue_exchange(rewl_plan* P) {
+    HIPCHK(P, launch_exchange(P->S, P->stream), "exchange launch");
+    return REWL_OK;
+}
+
+rewl_status enqueue_interval_batched(rewl_plan* P) {
+    rewl_status s = enqueue_sweep(P, P->interval);
+    if (s != REWL_OK) return s;
+    s = enqueue_boundary(P);
+    if (s != REWL_OK) return s;
+    return enqueue_exchange(P);
+}
+
+template <typename T>
+rewl_status d2h(rewl_plan* P, std::vector<T>& v, size_t off, size_t n) {
+    v.resize(n);
+    if (n == 0) return REWL_OK;
+    HIPCHK(P, hipMemcpyAsync(v.data(), static_cast<char*>(P->buf[REWL_BUF_STATE]) + off, n * sizeof(T),
+                             hipMemcpyDeviceToHost, P->stream), "state read");
+    return REWL_OK;
+}
+
+template <typename T>
+rewl_status h2d(rewl_plan* P, const std::vector<T>& v, size_t off) {
+    if (v.empty()) return REWL_OK;
+    HIPCHK(P, hipMemcpyAsync(static_cast<char*>(P->buf[REWL_BUF_STATE]) + off, v.data(), v.size() * sizeof(T),
+                             hipMemcpyHostToDevice, P->stream), "state write");
+    return REWL_OK;
+}
+
+// Plain form: one sweep launch per window, then flatness on the device, and
+// the stage decision and exchange arming on the host after a synchronisation
+// (the same rule as the batched stage kernel), then the exchange launch.
+rewl_status run_interval_plain(rewl_plan* P) {
+    const int wg = wg_of(P);
+    for (size_t p = 0; p < P->pd.size(); ++p) {
+        const PDesc& q = P->pd[p];
+        for (int w = 0; w < q.nwin; ++w) {
+            HIPCHK(P, launch_sweep(P->S, q.walker_off + static_cast<int64_t>(w) * q.W, q.W, P->interval,
+                                   q.L, wg, P->stream), "plain sweep launch");
+        }
+    }
+    HIPCHK(P, launch_flat(P->S, P->stream), "flatness launch");
+    const size_t np = P->pd.size();
+    std::vector<int32_t> stage, done, xon;
+    std::vector<int64_t> rnd, tstage, xr, t, lngb, tseen;
+    std::vector<uint32_t> flag;
+    rewl_status s;
+    if ((s = d2h(P, stage, P->off_stage, np)) || (s = d2h(P, done, P->off_done, np)) ||
+        (s = d2h(P, rnd, P->off_rnd, np)) || (s = d2h(P, tstage, P->off_tstage, np)) ||
+        (s = d2h(P, xr, P->off_xr, np)) || (s = d2h(P, xon, P->off_xon, np)) ||
+        (s = d2h(P, lngb, P->off_lngb, np)) || (s = d2h(P, tseen, P->off_tseen, np)) ||
+        (s = d2h(P, t, P->off_t, P->n_walk)) || (s = d2h(P, flag, P->off_flag, P->n_walk)))
+        return s;
+    HIPCHK(P, hipStreamSynchronize(P->stream), "plain boundary sync");
+    bool overflow = false;
+    for (size_t p = 0; p < np; ++p) {
+        const PDesc& q = P->pd[p];
+        if (done[p]) {
+            xon[p] = 0;
+            continue;
+        }
+        const int64_t tnow = t[q.walker_off];
+        const int64_t dt = tnow - tseen[p];
+        const int sh = q.K - stage[p];
+        const int64_t room = ((static_cast<int64_t>(1) << 62) - lngb[p]) >> sh;
+        if (dt > room) overflow = true;
+        else lngb[p] += dt << sh;
+        tseen[p] = tnow;
+        const int nw = q.nwin * q.W;
+        bool all = true;
+        for (int i = 0; i < nw; ++i) all = all && flag[q.walker_off + i] != 0;
+        const int64_t r = rnd[p];
+        if (all) {
+            if (stage[p] == q.K) {
+                done[p] = 1;
+                xon[p] = 0;
+                rnd[p] = r + 1;
+                continue;
+            }
+            stage[p] += 1;
+            tstage[p] = tnow;
+            for (int i = 0; i < nw; ++i) flag[q.walker_off + i] = 0;
+        }
+        xr[p] = r;
+        xon[p] = 1;
+        rnd[p] = r + 1;
+    }
+    if ((s = h2d(P, stage, P->off_stage)) || (s = h2d(P, done, P->off_done)) || (s = h2d(P, rnd, P->off_rnd)) ||
+        (s = h2d(P, tstage, P->off_tstage)) || (s = h2d(P, xr, P->off_xr)) || (s = h2d(P, xon, P->off_xon)) ||
+        (s = h2d(P, lngb, P->off_lngb)) || (s = h2d(P, tseen, P->off_tseen)) || (s = h2d(P, flag, P->off_flag)))
+        return s;
+    if (overflow) {
+        std::vector<int32_t> cnt;
+        if ((s = d2h(P, cnt, P->off_cnt, 4))) return s;
+        HIPCHK(P, hipStreamSynchronize(P->stream), "plain overflow sync");
+        cnt[1] |= ERR_OVERFLOW;
+        if ((s = h2d(P, cnt, P->off_cnt))) return s;
+    }
+    HIPCHK(P, launch_exchange(P->S, P->stream), "exchange launch");
+    // the host vectors above die here: keep the copies ordered before reuse
+    HIPCHK(P, hipStreamSynchronize(P->stream), "plain interval sync");
+    return REWL_OK;
+}
+
+rewl_status ensure_graph(rewl_plan* P, int G) {
+    if (P->graph && P->graph_g == G) return REWL_OK;
+    if (P->graph) {
+        (void)hipGraphExecDestroy(P->graph);
+        P->graph = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(P, hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal), "graph capture begin");
+    rewl_status s = REWL_OK;
+    for (int i = 0; i < G && s == REWL_OK; ++i) s = enqueue_interval_batched(P);
+    hipError_t e = hipStreamEndCapture(P->stream, &g);
+    if (s != REWL_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    if (e != hipSuccess) return dev_fail(P, e, "graph capture end");
+    e = hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return dev_fail(P, e, "graph instantiate");
+    P->graph_g = G;
+    return REWL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rewl_last_error(void) { return g_err.c_str(); }
+
+rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, const rewl_tuning* tuning,
+                             rewl_plan** out) {
+    if (!problems || !out || n_problems < 1) return fail(REWL_EINVAL, "problems/out must be non-null, n >= 1");
+    *out = nullptr;
+    for (int i = 0; i < n_problems; ++i) {
+        rewl_status s = validate(problems[i], i);
+        if (s != REWL_OK) return s;
+    }
+    rewl_tuning tn{};
+    if (tuning) {
+        tn = *tuning;
+        if (tn.form != REWL_FORM_BATCHED && tn.form != REWL_FORM_PLAIN) return fail(REWL_EINVAL, "unknown form");
+        if (tn.walkers_per_wg != 0 && tn.walkers_per_wg != 64 && tn.walkers_per_wg != 128 &&
+            tn.walkers_per_wg != 256)
+            return fail(REWL_EINVAL, "walkers_per_wg must be 0, 64, 128 or 256");
+        if (tn.graph_intervals < 0 || tn.graph_intervals > 4096) return fail(REWL_EINVAL, "graph_intervals 0..4096");
+        if (tn.grid_waves_per_cu < 0) return fail(REWL_EINVAL, "grid_waves_per_cu must be >= 0");
+        for (int r : tn.reserved)
+            if (r != 0) return fail(REWL_EINVAL, "tuning.reserved must be 0");
+    }
+    const int64_t X = problems[0].interval;
+    for (int i = 1; i < n_problems; ++i)
+        if (problems[i].interval != X) return fail(REWL_EINVAL, "all problems of a plan must share the interval");
+
+    rewl_plan* P = new (std::nothrow) rewl_plan();
+    if (!P) return fail(REWL_ENOMEM, "plan allocation");
+    P->probs.assign(problems, problems + n_problems);
+    P->tune = tn;
+    P->interval = X;
+    int64_t walker = 0;
+    uint64_t bins = 0, words = 0;
+    for (int p = 0; p < n_problems; ++p) {
+        const rewl_problem& q = problems[p];
+        PDesc d{};
+        d.L = q.L;
+        d.N = q.L * q.L;
+        d.K = q.k_final;
+        d.nwin = q.n_windows;
+        d.W = q.walkers_per_window;
+        d.flat_num = q.flat_num;
+        d.flat_den = q.flat_den;
+        d.row_words = (q.L + 31) / 32;
+        d.X = q.interval;
+        d.seed = q.seed;
+        d.walker_off = static_cast<int32_t>(walker);
+        d.init = q.init;
+        P->pd.push_back(d);
+        P->l_max = std::max(P->l_max, q.L);
+        std::vector<int> los, his;
+        for (int w = 0; w < q.n_windows; ++w) {
+            int lo, hi;
+            window_bounds(d.N, q.n_windows, q.overlap_num, q.overlap_den, w, lo, hi);
+            los.push_back(lo);
+            his.push_back(hi);
+            for (int a = 0; a < q.walkers_per_window; ++a) {
+                WDesc wd{};
+                wd.table_off = bins;
+                wd.spin_off = static_cast<uint32_t>(words);
+                wd.prob = p;
+                wd.lo = lo;
+                wd.hi = hi;
+                wd.win = w;
+                wd.gid = w * q.walkers_per_window + a;
+                P->wd.push_back(wd);
+                bins += static_cast<uint64_t>(hi - lo + 1) * (d.N + 1);
+                words += static_cast<uint64_t>(q.L) * d.row_words;
+                ++walker;
+            }
+            if (w + 1 < q.n_windows) P->pairs.push_back(PairDesc{p, w});
+        }
+        P->lo.push_back(los);
+        P->hi.push_back(his);
+        if (walker >= (1ll << 31) || words >= (1ull << 32)) {
+            delete P;
+            return fail(REWL_EINVAL, "too many walkers for one plan");
+        }
+    }
+    P->n_walk = walker;
+    P->n_bins = bins;
+    P->n_words = words;
+    const size_t A = 256;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes, A);
+        return at;
+    };
+    const size_t nw = static_cast<size_t>(walker), np = static_cast<size_t>(n_problems);
+    P->off_wd = take(nw * sizeof(WDesc));
+    P->off_pd = take(np * sizeof(PDesc));
+    P->off_pairs = take(std::max<size_t>(1, P->pairs.size()) * sizeof(PairDesc));
+    P->off_e = take(nw * 4);
+    P->off_m = take(nw * 4);
+    P->off_t = take(nw * 8);
+    P->off_te = take(nw * 8);
+    P->off_nseen = take(nw * 4);
+    P->off_flag = take(nw * 4);
+    P->off_scan = take(nw * 4);
+    P->off_stage = take(np * 4);
+    P->off_done = take(np * 4);
+    P->off_rnd = take(np * 8);
+    P->off_tstage = take(np * 8);
+    P->off_xr = take(np * 8);
+    P->off_xon = take(np * 4);
+    P->off_lngb = take(np * 8);
+    P->off_tseen = take(np * 8);
+    P->off_cnt = take(16);
+    P->sizes[REWL_BUF_TABLES] = align_up(bins * sizeof(Bin), A);
+    P->sizes[REWL_BUF_SPINS] = align_up(words * 4, A);
+    P->sizes[REWL_BUF_STATE] = o;
+    *out = P;
+    return REWL_OK;
+}
+
+void rewl_plan_destroy(rewl_plan* P) {
+    if (!P) return;
+    if (P->graph) (void)hipGraphExecDestroy(P->graph);
+    delete P;
+}
+
+rewl_status rewl_plan_buffer_sizes(const rewl_plan* P, size_t* sizes_out) {
+    if (!P || !sizes_out) return fail(REWL_EINVAL, "null argument");
+    for (int i = 0; i < REWL_NBUF; ++i) sizes_out[i] = P->sizes[i];
+    return REWL_OK;
+}
+
+rewl_status rewl_plan_counts(const rewl_plan* P, int32_t* n_problems, int64_t* n_walkers) {
+    if (!P) return fail(REWL_EINVAL, "null plan");
+    if (n_problems) *n_problems = static_cast<int32_t>(P->pd.size());
+    if (n_walkers) *n_walkers = P->n_walk;
+    return REWL_OK;
+}
+
+rewl_status rewl_window_bounds(const rewl_plan* P, int32_t prob, int32_t w, int32_t* e_lo, int32_t* e_hi) {
+    if (!P || !e_lo || !e_hi) return fail(REWL_EINVAL, "null argument");
+    if (prob < 0 || prob >= static_cast<int32_t>(P->pd.size())) return fail(REWL_EINVAL, "problem out of range");
+    if (w < 0 || w >= P->pd[prob].nwin) return fail(REWL_EINVAL, "window out of range");
+    *e_lo = P->lo[prob][w];
+    *e_hi = P->hi[prob][w];
+    return REWL_OK;
+}
+
+rewl_status rewl_plan_bind(rewl_plan* P, void* const* dev_ptrs, void* hip_stream) {
+    if (!P || !dev_ptrs) return fail(REWL_EINVAL, "null argument");
+    if (P->broken) return fail(REWL_ESTATE, "plan is in an error state");
+    for (int i = 0; i < REWL_NBUF; ++i) {
+        if (P->sizes[i] && !dev_ptrs[i]) return fail(REWL_EINVAL, "null device buffer");
+        if (reinterpret_cast<uintptr_t>(dev_ptrs[i]) % 256 != 0) return fail(REWL_EINVAL, "buffers must be 256-byte aligned");
+    }
+    for (int i = 0; i < REWL_NBUF; ++i) P->buf[i] = dev_ptrs[i];
+    P->stream = static_cast<hipStream_t>(hip_stream);
+    if (P->graph) {
+        (void)hipGraphExecDestroy(P->graph);
+        P->graph = nullptr;
+        P->graph_g = 0;
+    }
+    P->S = make_state(P);
+    HIPCHK(P, sweep_setup(), "kernel attributes");
+    char* st = static_cast<char*>(P->buf[REWL_BUF_STATE]);
+    HIPCHK(P, hipMemcpyAsync(st + P->off_wd, P->wd.data(), P->wd.size() * sizeof(WDesc), hipMemcpyHostToDevice,
+                             P->stream), "descriptor upload");
+    HIPCHK(P, hipMemcpyAsync(st + P->off_pd, P->pd.data(), P->pd.size() * sizeof(PDesc), hipMemcpyHostToDevice,
+                             P->stream), "descriptor upload");
+    if (!P->pairs.empty())
+        HIPCHK(P, hipMemcpyAsync(st + P->off_pairs, P->pairs.data(), P->pairs.size() * sizeof(PairDesc),
+                                 hipMemcpyHostToDevice, P->stream), "descriptor upload");
+    HIPCHK(P, hipStreamSynchronize(P->stream), "descriptor upload sync");
+    P->bound = true;
+    P->initialised = false;
+    return REWL_OK;
+}
+
+rewl_status rewl_init(rewl_plan* P) {
+    rewl_status s = usable(P);
+    if (s != REWL_OK) return s;
+    HIPCHK(P, launch_zero(P->buf[REWL_BUF_TABLES], P->sizes[REWL_BUF_TABLES], P->stream), "table clear");
+    HIPCHK(P, launch_zero(static_cast<char*>(P->buf[REWL_BUF_STATE]) + P->off_cnt, 16, P->stream), "counter clear");
+    HIPCHK(P, launch_init(P->S, P->stream), "init launch");
+    const int64_t cap_launch = 1 << 20;
+    const int64_t cap_total = 1ll << 40;
+    int64_t spent = 0;
+    for (;;) {
+        HIPCHK(P, launch_zero(static_cast<char*>(P->buf[REWL_BUF_STATE]) + P->off_cnt, 16, P->stream), "counter clear");
+        HIPCHK(P, launch_entry(P->S, cap_launch, P->stream), "entry launch");
+        int32_t cnt[4];
+        HIPCHK(P, hipMemcpyAsync(cnt, static_cast<char*>(P->buf[REWL_BUF_STATE]) + P->off_cnt, 16,
+                                 hipMemcpyDeviceToHost, P->stream), "entry counter read");
+        HIPCHK(P, hipStreamSynchronize(P->stream), "entry sync");
+        spent += cap_launch;
+        if (cnt[0] == 0) break;
+        if (spent >= cap_total) return fail(REWL_ESTATE, "entry walk exceeded 2^40 trials");
+    }
+    P->initialised = true;
+    return REWL_OK;
+}
+
+rewl_status rewl_sweep(rewl_plan* P, int64_t n) {
+    rewl_status s = usable(P);
+    if (s != REWL_OK) return s;
+    if (!P->initialised) return fail(REWL_ESTATE, "rewl_init has not run");
+    if (n < 0) return fail(REWL_EINVAL, "negative trial count");
+    if (P->tune.form == REWL_FORM_PLAIN) {
+        const int wg = wg_of(P);
+        for (const PDesc& q : P->pd)
+            for (int w = 0; w < q.nwin; ++w)
+                HIPCHK(P, launch_sweep(P->S, q.walker_off + static_cast<int64_t>(w) * q.W, q.W, n, q.L, wg,
+                                       P->stream), "plain sweep launch");
+        return REWL_OK;
+    }
+    return enqueue_sweep(P, n);
+}
+
+rewl_status rewl_reduce_lnf(rewl_plan* P) {
+    rewl_status s = usable(P);
+    if (s != REWL_OK) return s;
+    if (!P->initialised) return fail(REWL_ESTATE, "rewl_init has not run");
+    return enqueue_boundary(P);
+}
+
+rewl_status rewl_exchange(rewl_plan* P) {
+    rewl_status s = usable(P);
+    if (s != REWL_OK) return s;
+    if (!P->initialised) return fail(REWL_ESTATE, "rewl_init has not run");
+    return enqueue_exchange(P);
+}
+
+rewl_status rewl_run(rewl_plan* P, int64_t n) {
+    rewl_status s = usable(P);
+    if (s != REWL_OK) return s;
+    if (!P->initialised) return fail(REWL_ESTATE, "rewl_init has not run");
+    if (n < 0) return fail(REWL_EINVAL, "negative interval count");
+    if (P->tune.form == REWL_FORM_PLAIN) {
+        for (int64_t i = 0; i < n; ++i)
+            if ((s = run_interval_plain(P)) != REWL_OK) return s;
+        return REWL_OK;
+    }
+    const int G = P->tune.graph_intervals > 0 ? P->tune.graph_intervals : 8;
+    int64_t i = 0;
+    if (n >= G) {
+        if ((s = ensure_graph(P, G)) != REWL_OK) return s;
+        for (; i + G <= n; i += G) HIPCHK(P, hipGraphLaunch(P->graph, P->stream), "graph launch");
+    }
+    for (; i < n; ++i)
+        if ((s = enqueue_interval_batched(P)) != REWL_OK) return s;
+    return REWL_OK;
+}
+
+rewl_status rewl_query(rewl_plan* P, int32_t* stage_out, int32_t* done_out, int64_t* trials_out) {
+    rewl_status s = usable(P);
+    if (s != REWL_OK) return s;
+    const size_t np = P->pd.size();
+    std::vector<int32_t> stage, done, cnt;
+    std::vector<int64_t> t;
+    if ((s = d2h(P, stage, P->off_stage, np)) || (s = d2h(P, done, P->off_done, np)) ||
+        (s = d2h(P, t, P->off_t, P->n_walk)) || (s = d2h(P, cnt, P->off_cnt, 4)))
+        return s;
+    HIPCHK(P, hipStreamSynchronize(P->stream), "query sync");
+    for (size_t p = 0; p < np; ++p) {
+        if (stage_out) stage_out[p] = stage[p];
+        if (done_out) done_out[p] = done[p];
+        if (trials_out) trials_out[p] = t[P->pd[p].walker_off];
+    }
+    if (cnt[1] & ERR_OVERFLOW) return fail(REWL_EOVERFLOW, "ln g would exceed 2^62 units");
+    return REWL_OK;
+}
+
+rewl_status rewl_read_walker(rewl_plan* P, int32_t prob, int32_t w, int32_t a, int64_t* lng, uint64_t* H,
+                             size_t cap_bins, int8_t* spins, int32_t* e, int32_t* m, int64_t* t) {
+    rewl_status s = usable(P);
+    if (s != REWL_OK) return s;
+    if (prob < 0 || prob >= static_cast<int32_t>(P->pd.size())) return fail(REWL_EINVAL, "problem out of range");
+    const PDesc& q = P->pd[prob];
+    if (w < 0 || w >= q.nwin || a < 0 || a >= q.W) return fail(REWL_EINVAL, "walker out of range");
+    const int64_t g = q.walker_off + static_cast<int64_t>(w) * q.W + a;
+    const WDesc& d = P->wd[g];
+    const size_t nb = static_cast<size_t>(d.hi - d.lo + 1) * (q.N + 1);
+    if ((lng || H) && cap_bins < nb) return fail(REWL_EINVAL, "cap_bins too small");
+    std::vector<Bin> bins;
+    std::vector<uint32_t> words;
+    std::vector<int32_t> ev, mv, stage;
+    std::vector<int64_t> tv;
+    if (lng || H) {
+        bins.resize(nb);
+        HIPCHK(P, hipMemcpyAsync(bins.data(), static_cast<Bin*>(P->buf[REWL_BUF_TABLES]) + d.table_off,
+                                 nb * sizeof(Bin), hipMemcpyDeviceToHost, P->stream), "table read");
+    }
+    const size_t nwords = static_cast<size_t>(q.L) * q.row_words;
+    if (spins) {
+        words.resize(nwords);
+        HIPCHK(P, hipMemcpyAsync(words.data(), static_cast<uint32_t*>(P->buf[REWL_BUF_SPINS]) + d.spin_off,
+                                 nwords * 4, hipMemcpyDeviceToHost, P->stream), "spin read");
+    }
+    if ((s = d2h(P, ev, P->off_e, P->n_walk)) || (s = d2h(P, mv, P->off_m, P->n_walk)) ||
+        (s = d2h(P, tv, P->off_t, P->n_walk)) || (s = d2h(P, stage, P->off_stage, P->pd.size())))
+        return s;
+    HIPCHK(P, hipStreamSynchronize(P->stream), "walker read sync");
+    const uint64_t st = static_cast<uint64_t>(stage[prob]);
+    for (size_t i = 0; i < nb && (lng || H); ++i) {
+        if (lng) lng[i] = bins[i].lng;
+        if (H) H[i] = ((bins[i].hs & STAMP_MASK) == st) ? (bins[i].hs >> STAMP_BITS) : 0;
+    }
+    if (spins)
+        for (int r = 0; r < q.L; ++r)
+            for (int c = 0; c < q.L; ++c)
+                spins[r * q.L + c] = ((words[r * q.row_words + (c >> 5)] >> (c & 31)) & 1u) ? 1 : -1;
+    if (e) *e = ev[g];
+    if (m) *m = mv[g];
+    if (t) *t = tv[g];
+    return REWL_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+rewl_status rewl_lnz_forward(const double* lng, int32_t N, int32_t e0, int32_t nE, int32_t m0, int32_t nM,
+                             const double* beta, const double* h, int64_t G, double* lnz, void* hip_stream) {
+    if (!lng || !beta || !h || !lnz) return fail(REWL_EINVAL, "null pointer");
+    if (N < 1 || nE < 1 || nM < 1 || e0 < 0 || m0 < 0 || e0 + nE > N + 1 || m0 + nM > N + 1 || G < 0)
+        return fail(REWL_EINVAL, "bad reweighting geometry");
+    hipError_t e = launch_lnz_forward(lng, N, e0, nE, m0, nM, beta, h, G, lnz, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(REWL_EDEVICE, std::string("lnz forward: ") + hipGetErrorString(e));
+    return REWL_OK;
+}
+
+rewl_status rewl_lnz_backward(const double* lng, int32_t N, int32_t e0, int32_t nE, int32_t m0, int32_t nM,
+                              const double* beta, const double* h, int64_t G, const double* lnz,
+                              const double* grad_out, double* grad_beta, double* grad_h, double* grad_lng,
+                              double* mom, int32_t order, void* hip_stream) {
+    if (!lng || !beta || !h || !lnz) return fail(REWL_EINVAL, "null pointer");
+    if (N < 1 || nE < 1 || nM < 1 || e0 < 0 || m0 < 0 || e0 + nE > N + 1 || m0 + nM > N + 1 || G < 0)
+        return fail(REWL_EINVAL, "bad reweighting geometry");
+    if (order != 1 && order != 2) return fail(REWL_EINVAL, "order must be 1 or 2");
+    if (order == 2 && !mom) return fail(REWL_EINVAL, "order 2 needs mom");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipError_t e;
+    if (order == 1) {
+        e = launch_lnz_moments(lng, N, e0, nE, m0, nM, beta, h, G, lnz, grad_out, mom, grad_beta, grad_h, st);
+        if (e == hipSuccess && grad_lng)
+            e = launch_lnz_grad_lng(lng, N, e0, nE, m0, nM, beta, h, G, lnz, grad_out, grad_lng, st);
+    } else {
+        e = launch_lnz_moments(lng, N, e0, nE, m0, nM, beta, h, G, lnz, nullptr, mom, nullptr, nullptr, st);
+    }
+    if (e != hipSuccess) return fail(REWL_EDEVICE, std::string("lnz backward: ") + hipGetErrorString(e));
+    return REWL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,548 @@
+// rewl_kernels.hip -- gfx950 kernels of two-dimensional replica-exchange
+// Wang-Landau sampling of the periodic L x L Ising model (Valentim et al.,
+// arXiv:1508.02748, Sec. 2).
+//
+// Layout (one lane = one walker; no checkerboard: each walker's chain of
+// trials is sequential, and the wavefront's 64 lanes run 64 independent
+// walkers):
+//   * spins: L rows of L bits, bit-packed, one 32- or 64-bit word per row.
+//     During a sweep they live in LDS as lds[row * WG + lane] so that any mix
+//     of rows read by the 64 lanes hits 64 distinct consecutive words (no bank
+//     conflicts); in HBM they are packed per walker (row_words words per row).
+//   * ln g / H: one table per walker (single owner, no atomics), window rows
+//     e in [lo, hi] by all m in [0, N], 16-byte bins {ln g, H << 6 | stage}.
+//     The walker keeps the bin it currently occupies in registers and writes
+//     it back only when it leaves, so a trial costs one 16-byte gather of the
+//     proposed bin plus, on acceptance, one 16-byte store.
+//   * random numbers: Philox4x32-10 addressed by (seed; attempt block, walker,
+//     stream tag); one block serves two consecutive trials.
+#include <hip/hip_runtime.h>
+
+#include "rewl_internal.h"
+
+namespace rewl {
+namespace {
+
+constexpr uint32_t TAG_WL = 0, TAG_INIT = 1, TAG_ENTRY = 2, TAG_XPERM = 3, TAG_XACC = 4;
+
+struct Words4 {
+    uint32_t x, y, z, w;
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32 -> 64 multiplies mixing the counter with a Weyl-incremented key.
+__device__ __forceinline__ Words4 philox4x32_10(uint64_t key, uint32_t c0, uint32_t c1,
+                                                uint32_t c2, uint32_t c3) {
+    uint32_t k0 = static_cast<uint32_t>(key);
+    uint32_t k1 = static_cast<uint32_t>(key >> 32);
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t a_lo = 0xD2511F53u * c0;
+        const uint32_t a_hi = __umulhi(0xD2511F53u, c0);
+        const uint32_t b_lo = 0xCD9E8D57u * c2;
+        const uint32_t b_hi = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = b_hi ^ c1 ^ k0;
+        const uint32_t n2 = a_hi ^ c3 ^ k1;
+        c0 = n0;
+        c1 = b_lo;
+        c2 = n2;
+        c3 = a_lo;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// exp(x) for -23 < x <= 0, as a fixed sequence of correctly rounded IEEE
+// operations: x = k ln2 + r (k nearest to x / ln2, ln2 split into a 32-bit
+// head and a tail so k * head is exact), exp(r) by its degree-13 Taylor
+// polynomial in Horner form with fused multiply-adds, then scaling by 2^k.
+__device__ __forceinline__ double exp_neg(double x) {
+    const double log2e = 1.4426950408889634;                  // RN(1 / ln 2)
+    const double ln2_head = 2977044471.0 / 4294967296.0;      // floor(ln 2 * 2^32) / 2^32
+    const double ln2_tail = 1.9082149292705877e-10;           // RN(ln 2 - head)
+    const double k = floor(__dadd_rn(__dmul_rn(x, log2e), 0.5));
+    double r = __fma_rn(-k, ln2_head, x);
+    r = __fma_rn(-k, ln2_tail, r);
+    double p = 1.0 / 6227020800.0;                            // 1/13!
+    p = __fma_rn(p, r, 1.0 / 479001600.0);
+    p = __fma_rn(p, r, 1.0 / 39916800.0);
+    p = __fma_rn(p, r, 1.0 / 3628800.0);
+    p = __fma_rn(p, r, 1.0 / 362880.0);
+    p = __fma_rn(p, r, 1.0 / 40320.0);
+    p = __fma_rn(p, r, 1.0 / 5040.0);
+    p = __fma_rn(p, r, 1.0 / 720.0);
+    p = __fma_rn(p, r, 1.0 / 120.0);
+    p = __fma_rn(p, r, 1.0 / 24.0);
+    p = __fma_rn(p, r, 1.0 / 6.0);
+    p = __fma_rn(p, r, 0.5);
+    p = __fma_rn(p, r, 1.0);
+    p = __fma_rn(p, r, 1.0);
+    return ldexp(p, static_cast<int>(k));
+}
+
+// Acceptance with probability min[1, exp(delta 2^-K)] (Eq. 1 and Eq. 2 with
+// ln g in fixed point): u = (w + 1/2) 2^-32 >= 2^-33 > e^-23, so a ratio
+// below e^-23 is always a rejection.
+__device__ __forceinline__ bool accept_move(int64_t delta, uint32_t u_word, int K) {
+    if (delta >= 0) return true;
+    if (delta <= -(static_cast<int64_t>(23) << K)) return false;
+    const double x = ldexp(static_cast<double>(delta), -K);
+    const double u = __dmul_rn(__dadd_rn(static_cast<double>(u_word), 0.5), 1.0 / 4294967296.0);
+    return u < exp_neg(x);
+}
+
+__device__ __forceinline__ uint32_t gbit(const uint32_t* sp, int rw, int r, int c) {
+    return (sp[r * rw + (c >> 5)] >> (c & 31)) & 1u;
+}
+
+__device__ __forceinline__ void gflip(uint32_t* sp, int rw, int r, int c) {
+    sp[r * rw + (c >> 5)] ^= 1u << (c & 31);
+}
+
+// (row, column) of the site floor(w N / 2^32), N = L*L, without a division:
+// w L = r 2^32 + q  gives  w N / 2^32 = r L + q L / 2^32.
+__device__ __forceinline__ void site_rc(uint32_t w, int L, int& r, int& c) {
+    const uint64_t x = static_cast<uint64_t>(w) * static_cast<uint32_t>(L);
+    r = static_cast<int>(x >> 32);
+    c = static_cast<int>((static_cast<uint64_t>(static_cast<uint32_t>(x)) * static_cast<uint32_t>(L)) >> 32);
+}
+
+// ------------------------------------------------------------------ zero fill
+__global__ void k_zero(uint4* p, size_t n16) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride)
+        p[i] = make_uint4(0, 0, 0, 0);
+}
+
+// ------------------------------------------------------------------ init
+// Initial configuration: site 128q + 32j + k takes bit k of word j of the
+// INIT block q of the walker (1 = up), or all up; then E, M and a clean state.
+__global__ void k_init(DevState S) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= S.n_walk) return;
+    const WDesc d = S.wd[g];
+    const PDesc P = S.pd[d.prob];
+    const int L = P.L, N = P.N, rw = P.row_words;
+    uint32_t* sp = S.spins + d.spin_off;
+    for (int i = 0; i < L * rw; ++i) sp[i] = 0;
+    if (P.init == 1) {
+        for (int r = 0; r < L; ++r)
+            for (int c = 0; c < L; ++c) sp[r * rw + (c >> 5)] |= 1u << (c & 31);
+    } else {
+        for (int q = 0; 128 * q < N; ++q) {
+            const Words4 b = philox4x32_10(P.seed, static_cast<uint32_t>(q), 0u,
+                                           static_cast<uint32_t>(d.gid), TAG_INIT << 24);
+            const uint32_t ws[4] = {b.x, b.y, b.z, b.w};
+            for (int j = 0; j < 4; ++j)
+                for (int k = 0; k < 32; ++k) {
+                    const int site = 128 * q + 32 * j + k;
+                    if (site < N && ((ws[j] >> k) & 1u)) {
+                        const int r = site / L, c = site % L;
+                        sp[r * rw + (c >> 5)] |= 1u << (c & 31);
+                    }
+                }
+        }
+    }
+    int E = 0, M = 0;
+    for (int r = 0; r < L; ++r)
+        for (int c = 0; c < L; ++c) {
+            const int s0 = 2 * static_cast<int>(gbit(sp, rw, r, c)) - 1;
+            const int sr = 2 * static_cast<int>(gbit(sp, rw, r, c + 1 == L ? 0 : c + 1)) - 1;
+            const int sd = 2 * static_cast<int>(gbit(sp, rw, r + 1 == L ? 0 : r + 1, c)) - 1;
+            E -= s0 * (sr + sd);
+            M += s0;
+        }
+    S.e[g] = (E + 2 * N) / 4;
+    S.m[g] = (M + N) / 2;
+    S.t[g] = 0;
+    S.te[g] = 0;
+    S.nseen[g] = 0;
+    S.flag[g] = 0;
+    S.scan[g] = 0;
+    if (d.gid == 0) {
+        const int p = d.prob;
+        S.stage[p] = 0;
+        S.done[p] = 0;
+        S.rnd[p] = 0;
+        S.tstage[p] = 0;
+        S.xr[p] = 0;
+        S.xon[p] = 0;
+        S.lngb[p] = 0;
+        S.tseen[p] = 0;
+    }
+}
+
+// ------------------------------------------------------------------ entry
+// Walk each walker into its energy window: Metropolis at unit temperature on
+// the distance d (bins) to the window; a flip that does not increase d is
+// taken, one that increases it by k bins with probability exp(-4k).
+__device__ __forceinline__ int win_dist(int e, int lo, int hi) {
+    return e < lo ? lo - e : (e > hi ? e - hi : 0);
+}
+
+__global__ void k_entry(DevState S, int64_t cap) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= S.n_walk) return;
+    const WDesc d = S.wd[g];
+    const PDesc P = S.pd[d.prob];
+    int e = S.e[g], m = S.m[g];
+    int dist = win_dist(e, d.lo, d.hi);
+    if (dist == 0) return;
+    const int L = P.L, rw = P.row_words, K = P.K;
+    uint32_t* sp = S.spins + d.spin_off;
+    int64_t te = S.te[g];
+    for (int64_t i = 0; i < cap && dist > 0; ++i) {
+        const uint64_t blk = static_cast<uint64_t>(te) >> 1;
+        const Words4 b = philox4x32_10(P.seed, static_cast<uint32_t>(blk), static_cast<uint32_t>(blk >> 32),
+                                       static_cast<uint32_t>(d.gid), TAG_ENTRY << 24);
+        const uint32_t sw = (te & 1) ? b.z : b.x;
+        const uint32_t uw = (te & 1) ? b.w : b.y;
+        int r, c;
+        site_rc(sw, L, r, c);
+        const uint32_t bc = gbit(sp, rw, r, c);
+        const uint32_t k = (gbit(sp, rw, r, c == 0 ? L - 1 : c - 1) ^ bc) +
+                           (gbit(sp, rw, r, c == L - 1 ? 0 : c + 1) ^ bc) +
+                           (gbit(sp, rw, r == 0 ? L - 1 : r - 1, c) ^ bc) +
+                           (gbit(sp, rw, r == L - 1 ? 0 : r + 1, c) ^ bc);
+        const int e2 = e + 2 - static_cast<int>(k);
+        const int m2 = m + 1 - 2 * static_cast<int>(bc);
+        const int dist2 = win_dist(e2, d.lo, d.hi);
+        const bool acc = dist2 <= dist ||
+                         accept_move(-static_cast<int64_t>(4 * (dist2 - dist)) * (static_cast<int64_t>(1) << K),
+                                     uw, K);
+        if (acc) {
+            gflip(sp, rw, r, c);
+            e = e2;
+            m = m2;
+            dist = dist2;
+        }
+        ++te;
+    }
+    S.e[g] = e;
+    S.m[g] = m;
+    S.te[g] = te;
+    if (dist > 0) atomicAdd(&S.counters[0], 1);
+}
+
+// ------------------------------------------------------------------ sweep
+// n_trials Wang-Landau trials (Eq. 1) for each walker g in
+// [g_begin, g_begin + g_count) of an unfinished problem.  Each lane owns one
+// walker; its spins sit in LDS column `lane`.  No lane touches another's data,
+// so the kernel has no barriers.
+template <typename RowT>
+__global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int64_t g_count,
+                                               int64_t n_trials) {
+    extern __shared__ unsigned char lds_raw[];
+    RowT* lds = reinterpret_cast<RowT*>(lds_raw);
+    const int lane = threadIdx.x;
+    const int WG = blockDim.x;
+    const int64_t gi = static_cast<int64_t>(blockIdx.x) * WG + lane;
+    if (gi >= g_count) return;
+    const int64_t g = g_begin + gi;
+    const WDesc d = S.wd[g];
+    const int p = d.prob;
+    if (S.done[p]) return;
+    const PDesc P = S.pd[p];
+    const int L = P.L, K = P.K, rw = P.row_words;
+    const int s = S.stage[p];
+    const int64_t inc = static_cast<int64_t>(1) << (K - s);
+    const int lo = d.lo, hi = d.hi;
+    const uint64_t stride = static_cast<uint64_t>(P.N) + 1;
+    const uint64_t seed = P.seed;
+    const uint32_t gid = static_cast<uint32_t>(d.gid);
+    Bin* tab = S.tables + d.table_off;
+
+    const uint32_t* gsp = S.spins + d.spin_off;
+    for (int r = 0; r < L; ++r) {
+        RowT v = static_cast<RowT>(gsp[r * rw]);
+        if constexpr (sizeof(RowT) == 8) {
+            if (rw == 2) v |= static_cast<RowT>(gsp[2 * r + 1]) << 32;
+        }
+        lds[r * WG + lane] = v;
+    }
+
+    int e = S.e[g], m = S.m[g];
+    int64_t t = S.t[g];
+    uint32_t nseen = S.nseen[g];
+    uint64_t cur = static_cast<uint64_t>(e - lo) * stride + static_cast<uint64_t>(m);
+    Bin cb = tab[cur];
+    int64_t lng_cur = cb.lng;
+    uint64_t h_cur = ((cb.hs & STAMP_MASK) == static_cast<uint64_t>(s)) ? (cb.hs >> STAMP_BITS) : 0;
+
+    Words4 blk = {0, 0, 0, 0};
+    for (int64_t i = 0; i < n_trials; ++i) {
+        if (i == 0 || (t & 1) == 0) {
+            const uint64_t b = static_cast<uint64_t>(t) >> 1;
+            blk = philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid, TAG_WL << 24);
+        }
+        const uint32_t sw = (t & 1) ? blk.z : blk.x;
+        const uint32_t uw = (t & 1) ? blk.w : blk.y;
+        int r, c;
+        site_rc(sw, L, r, c);
+        const int ru = r == 0 ? L - 1 : r - 1;
+        const int rd = r == L - 1 ? 0 : r + 1;
+        const int cl = c == 0 ? L - 1 : c - 1;
+        const int cr = c == L - 1 ? 0 : c + 1;
+        const RowT row = lds[r * WG + lane];
+        const RowT rowu = lds[ru * WG + lane];
+        const RowT rowd = lds[rd * WG + lane];
+        const uint32_t bc = static_cast<uint32_t>(row >> c) & 1u;
+        // number of the four neighbours anti-aligned with the site
+        const uint32_t k = ((static_cast<uint32_t>(row >> cl) & 1u) ^ bc) +
+                           ((static_cast<uint32_t>(row >> cr) & 1u) ^ bc) +
+                           ((static_cast<uint32_t>(rowu >> c) & 1u) ^ bc) +
+                           ((static_cast<uint32_t>(rowd >> c) & 1u) ^ bc);
+        const int e2 = e + 2 - static_cast<int>(k);    // dE = 8 - 4k
+        const int m2 = m + 1 - 2 * static_cast<int>(bc);  // dM = -2 s
+        if (e2 >= lo && e2 <= hi) {
+            const uint64_t idx2 = static_cast<uint64_t>(e2 - lo) * stride + static_cast<uint64_t>(m2);
+            const Bin tb = tab[idx2];
+            if (accept_move(lng_cur - tb.lng, uw, K)) {
+                tab[cur] = Bin{lng_cur, (h_cur << STAMP_BITS) | static_cast<uint64_t>(s)};
+                lds[r * WG + lane] = row ^ (static_cast<RowT>(1) << c);
+                e = e2;
+                m = m2;
+                cur = idx2;
+                lng_cur = tb.lng;
+                h_cur = ((tb.hs & STAMP_MASK) == static_cast<uint64_t>(s)) ? (tb.hs >> STAMP_BITS) : 0;
+            }
+        }
+        nseen += (lng_cur == 0) ? 1u : 0u;
+        lng_cur += inc;
+        h_cur += 1;
+        ++t;
+    }
+    tab[cur] = Bin{lng_cur, (h_cur << STAMP_BITS) | static_cast<uint64_t>(s)};
+    S.e[g] = e;
+    S.m[g] = m;
+    S.t[g] = t;
+    S.nseen[g] = nseen;
+    uint32_t* osp = S.spins + d.spin_off;
+    for (int r = 0; r < L; ++r) {
+        const RowT v = lds[r * WG + lane];
+        osp[r * rw] = static_cast<uint32_t>(v);
+        if constexpr (sizeof(RowT) == 8) {
+            if (rw == 2) osp[2 * r + 1] = static_cast<uint32_t>(v >> 32);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ flatness
+// One wavefront per walker scans its table 64 bins at a time, starting where
+// the previous scan failed: the walker is flat iff every visited bin (ln g >
+// 0) has flat_den * H * n_seen >= flat_num * sum H, with sum H = trials made
+// in this stage.  The first failing chunk ends the scan; the latch is set only
+// after a full pass.
+__global__ void __launch_bounds__(256) k_flat(DevState S) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * 4 + wave;
+    if (g >= S.n_walk) return;
+    const WDesc d = S.wd[g];
+    const int p = d.prob;
+    if (S.done[p] || S.flag[g]) return;
+    const PDesc P = S.pd[p];
+    const uint64_t s = static_cast<uint64_t>(S.stage[p]);
+    const uint64_t n = S.nseen[g];
+    const uint64_t sum = static_cast<uint64_t>(S.t[g] - S.tstage[p]);
+    if (n == 0) return;
+    const Bin* tab = S.tables + d.table_off;
+    const int64_t nb = static_cast<int64_t>(d.hi - d.lo + 1) * (P.N + 1);
+    const int64_t nch = (nb + 63) / 64;
+    int64_t c0 = S.scan[g];
+    if (c0 >= nch) c0 = 0;
+    const unsigned __int128 rhs = static_cast<unsigned __int128>(static_cast<uint64_t>(P.flat_num)) * sum;
+    for (int64_t k = 0; k < nch; ++k) {
+        int64_t c = c0 + k;
+        if (c >= nch) c -= nch;
+        const int64_t i = c * 64 + lane;
+        int fail = 0;
+        if (i < nb) {
+            const Bin b = tab[i];
+            if (b.lng != 0) {
+                const uint64_t H = ((b.hs & STAMP_MASK) == s) ? (b.hs >> STAMP_BITS) : 0;
+                fail = static_cast<unsigned __int128>(static_cast<uint64_t>(P.flat_den)) * H * n < rhs;
+            }
+        }
+        if (__any(fail)) {
+            if (lane == 0) S.scan[g] = static_cast<uint32_t>(c);
+            return;
+        }
+    }
+    if (lane == 0) S.flag[g] = 1;
+}
+
+// ------------------------------------------------------------------ stage
+// Per problem: when every walker is flat, all move to the next stage together
+// (ln f halves; H restarts from zero through the stage stamp); flatness at
+// the last stage ends the problem.  Otherwise the boundary's exchange round
+// is armed.  Also guards the int64 headroom of ln g.
+__global__ void k_stage(DevState S) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= S.n_prob) return;
+    if (S.done[p]) {
+        S.xon[p] = 0;
+        return;
+    }
+    const PDesc P = S.pd[p];
+    // every ln g entry is at most the sum of all increments made so far
+    const int64_t tnow = S.t[P.walker_off];
+    const int64_t dt = tnow - S.tseen[p];
+    const int sh = P.K - S.stage[p];
+    const int64_t room = ((static_cast<int64_t>(1) << 62) - S.lngb[p]) >> sh;
+    if (dt > room) atomicOr(&S.counters[1], ERR_OVERFLOW);
+    else S.lngb[p] += dt << sh;
+    S.tseen[p] = tnow;
+    const int nw = P.nwin * P.W;
+    bool all = true;
+    for (int i = 0; i < nw; ++i) all = all && (S.flag[P.walker_off + i] != 0);
+    const int64_t r = S.rnd[p];
+    if (all) {
+        if (S.stage[p] == P.K) {
+            S.done[p] = 1;
+            S.xon[p] = 0;
+            S.rnd[p] = r + 1;
+            return;
+        }
+        S.stage[p] += 1;
+        S.tstage[p] = S.t[P.walker_off];
+        for (int i = 0; i < nw; ++i) S.flag[P.walker_off + i] = 0;
+    }
+    S.xr[p] = r;
+    S.xon[p] = 1;
+    S.rnd[p] = r + 1;
+}
+
+// ------------------------------------------------------------------ exchange
+// One workgroup per adjacent window pair (w, w+1) of a problem; pairs with
+// w = r (mod 2) act in round r (Sec. 2, Eq. 2).  Lane 0 draws the random
+// matching (Fisher-Yates from the XPERM stream), tests that both
+// configurations lie in the overlap, and accepts with
+// min[1, g_A(X) g_B(Y) / (g_A(Y) g_B(X))]; then the workgroup swaps the
+// accepted configurations.  ln g and H do not change.
+__global__ void __launch_bounds__(64) k_exchange(DevState S) {
+    __shared__ int perm[256];
+    __shared__ int32_t acc_a[256], acc_b[256];
+    __shared__ int n_acc;
+    const PairDesc pr = S.pairs[blockIdx.x];
+    const int p = pr.prob, w = pr.w;
+    if (!S.xon[p]) return;
+    const int64_t r = S.xr[p];
+    if ((w & 1) != static_cast<int>(r & 1)) return;
+    const PDesc P = S.pd[p];
+    const int W = P.W;
+    if (threadIdx.x == 0) {
+        const uint32_t r_lo = static_cast<uint32_t>(r), r_hi = static_cast<uint32_t>(static_cast<uint64_t>(r) >> 32);
+        for (int a = 0; a < W; ++a) perm[a] = a;
+        for (int i = W - 1; i >= 1; --i) {
+            const Words4 b = philox4x32_10(P.seed, r_lo, r_hi, static_cast<uint32_t>(w),
+                                           (TAG_XPERM << 24) | static_cast<uint32_t>(i));
+            const int j = static_cast<int>((static_cast<uint64_t>(b.x) * static_cast<uint64_t>(i + 1)) >> 32);
+            const int tmp = perm[i];
+            perm[i] = perm[j];
+            perm[j] = tmp;
+        }
+        const uint64_t stride = static_cast<uint64_t>(P.N) + 1;
+        int n = 0;
+        for (int a = 0; a < W; ++a) {
+            const int A = P.walker_off + w * W + a;
+            const int B = P.walker_off + (w + 1) * W + perm[a];
+            const WDesc dA = S.wd[A], dB = S.wd[B];
+            const int eA = S.e[A], mA = S.m[A], eB = S.e[B], mB = S.m[B];
+            if (eA < dB.lo || eA > dB.hi || eB < dA.lo || eB > dA.hi) continue;
+            const Bin* tA = S.tables + dA.table_off;
+            const Bin* tB = S.tables + dB.table_off;
+            const int64_t delta =
+                tA[static_cast<uint64_t>(eA - dA.lo) * stride + mA].lng -
+                tA[static_cast<uint64_t>(eB - dA.lo) * stride + mB].lng +
+                tB[static_cast<uint64_t>(eB - dB.lo) * stride + mB].lng -
+                tB[static_cast<uint64_t>(eA - dB.lo) * stride + mA].lng;
+            const Words4 b = philox4x32_10(P.seed, r_lo, r_hi, static_cast<uint32_t>(w),
+                                           (TAG_XACC << 24) | static_cast<uint32_t>(a));
+            if (accept_move(delta, b.x, P.K)) {
+                S.e[A] = eB;
+                S.m[A] = mB;
+                S.e[B] = eA;
+                S.m[B] = mA;
+                acc_a[n] = A;
+                acc_b[n] = B;
+                ++n;
+            }
+        }
+        n_acc = n;
+    }
+    __syncthreads();
+    const int words = P.L * P.row_words;
+    for (int k = 0; k < n_acc; ++k) {
+        uint32_t* sa = S.spins + S.wd[acc_a[k]].spin_off;
+        uint32_t* sb = S.spins + S.wd[acc_b[k]].spin_off;
+        for (int i = threadIdx.x; i < words; i += blockDim.x) {
+            const uint32_t tmp = sa[i];
+            sa[i] = sb[i];
+            sb[i] = tmp;
+        }
+    }
+}
+
+int blocks_for(int64_t n, int per) { return static_cast<int>((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    int grid = static_cast<int>((n16 + 255) / 256);
+    if (grid > 65536) grid = 65536;
+    hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, st, static_cast<uint4*>(p), n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const DevState& S, hipStream_t st) {
+    hipLaunchKernelGGL(k_init, dim3(blocks_for(S.n_walk, 64)), dim3(64), 0, st, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_entry(const DevState& S, int64_t cap, hipStream_t st) {
+    hipLaunchKernelGGL(k_entry, dim3(blocks_for(S.n_walk, 64)), dim3(64), 0, st, S, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int64_t n_trials,
+                        int l_max, int wg, hipStream_t st) {
+    if (g_count <= 0 || n_trials <= 0) return hipSuccess;
+    const int grid = blocks_for(g_count, wg);
+    if (l_max <= 32) {
+        const size_t lds = static_cast<size_t>(l_max) * wg * sizeof(uint32_t);
+        hipLaunchKernelGGL(k_sweep<uint32_t>, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials);
+    } else {
+        const size_t lds = static_cast<size_t>(l_max) * wg * sizeof(uint64_t);
+        hipLaunchKernelGGL(k_sweep<uint64_t>, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials);
+    }
+    return hipGetLastError();
+}
+
+hipError_t sweep_setup() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep<uint32_t>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep<uint64_t>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+hipError_t launch_flat(const DevState& S, hipStream_t st) {
+    hipLaunchKernelGGL(k_flat, dim3(blocks_for(S.n_walk, 4)), dim3(256), 0, st, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage(const DevState& S, hipStream_t st) {
+    hipLaunchKernelGGL(k_stage, dim3(blocks_for(S.n_prob, 64)), dim3(64), 0, st, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_exchange(const DevState& S, hipStream_t st) {
+    if (S.n_pairs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_exchange, dim3(S.n_pairs), dim3(64), 0, st, S);
+    return hipGetLastError();
+}
+
+}  // namespace rewl

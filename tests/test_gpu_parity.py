@@ -1,0 +1,183 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Spins, E, M, ln g (int64 fixed point), H, trial counts, stages and the done
+flag must be identical, walker by walker, under the same Philox stream: the
+acceptance is the same fixed sequence of IEEE operations on both sides, so
+there is no tolerance.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.rewl import OracleREWL
+
+pytestmark = pytest.mark.gpu
+
+
+def _R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1508_02748_amd as R
+    R.lib()
+    return R
+
+
+def _oracle_of(p):
+    o = OracleREWL(p.L, p.n_windows, p.overlap, p.walkers_per_window, p.k_final, p.flat, p.interval,
+                   p.seed, p.init)
+    o.init()
+    return o
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def compare(plan, pi, orc, tables=True, walkers=None):
+    p = plan.problems[pi]
+    gs = range(orc.n_walkers) if walkers is None else walkers
+    for g in gs:
+        w, a = divmod(g, p.walkers_per_window)
+        dg = plan.walker(pi, w, a, tables=tables)
+        do = orc.walker(g, tables=tables)
+        assert (dg["e"], dg["m"], dg["t"]) == (do["e"], do["m"], do["t"]), (pi, g)
+        assert (dg["spins"] == do["spins"]).all(), (pi, g)
+        if tables:
+            assert (dg["lng"] == do["lng"]).all(), (pi, g, "lng")
+            assert (dg["H"] == do["H"].astype(np.uint64)).all(), (pi, g, "H")
+    q = plan.query()
+    info = orc.info()
+    assert int(q["stage"][pi]) == info["stage"] and bool(q["done"][pi]) == info["done"], (q, info)
+
+
+def test_c1_serial_wl_full_run_bit_exact():
+    R = _R()
+    p = R.Problem(L=4, n_windows=1, walkers_per_window=1, k_final=16, interval=10_000, seed=0)
+    _say("case: C1 4x4 serial 2D-WL, K=16, full run")
+    plan = R.Plan([p])
+    plan.init()
+    orc = _oracle_of(p)
+    compare(plan, 0, orc)
+    for _ in range(100):
+        plan.run(16)
+        orc.run(16)
+        compare(plan, 0, orc)
+        if orc.info()["done"]:
+            break
+    assert orc.info()["done"] and bool(plan.query()["done"][0])
+    # finished problems stop changing
+    plan.run(5)
+    compare(plan, 0, orc)
+
+
+def test_c2_rewl_16x16_prefix_bit_exact():
+    R = _R()
+    p = R.Problem(L=16, n_windows=8, walkers_per_window=4, k_final=20, interval=10_000, seed=0)
+    _say("case: C2 16x16 REWL 8x4, 48 intervals, batched graph G=8")
+    plan = R.Plan([p], R.Tuning(graph_intervals=8))
+    plan.init()
+    orc = _oracle_of(p)
+    compare(plan, 0, orc)
+    for _ in range(3):
+        plan.run(16)
+        orc.run(16)
+        compare(plan, 0, orc)
+
+
+def test_plain_form_equals_batched_and_oracle():
+    R = _R()
+    p = R.Problem(L=8, n_windows=3, walkers_per_window=2, k_final=8, interval=1000, seed=5)
+    _say("case: plain vs batched, 8x8 3x2, K=8")
+    plain = R.Plan([p], R.Tuning(form=R.FORM_PLAIN))
+    batched = R.Plan([p], R.Tuning(graph_intervals=4))
+    plain.init()
+    batched.init()
+    orc = _oracle_of(p)
+    for _ in range(6):
+        plain.run(40)
+        batched.run(40)
+        orc.run(40)
+        compare(plain, 0, orc)
+        compare(batched, 0, orc)
+
+
+def test_mixed_lattice_batch_one_launch():
+    R = _R()
+    probs = [R.Problem(L=8, n_windows=2, walkers_per_window=3, k_final=12, interval=2000, seed=11),
+             R.Problem(L=12, n_windows=4, walkers_per_window=2, k_final=12, interval=2000, seed=12),
+             R.Problem(L=16, n_windows=8, walkers_per_window=1, k_final=12, interval=2000, seed=13),
+             R.Problem(L=24, n_windows=5, walkers_per_window=2, k_final=12, interval=2000, seed=14, init=1),
+             R.Problem(L=32, n_windows=3, walkers_per_window=2, k_final=12, interval=2000, seed=15)]
+    _say("case: mixed batch L in {8,12,16,24,32}, uneven windows")
+    plan = R.Plan(probs, R.Tuning(graph_intervals=3))
+    plan.init()
+    orcs = [_oracle_of(p) for p in probs]
+    for i, o in enumerate(orcs):
+        compare(plan, i, o)
+    plan.run(7)
+    for i, o in enumerate(orcs):
+        o.run(7)
+        compare(plan, i, o)
+
+
+@pytest.mark.parametrize("wg,G", [(64, 1), (128, 5), (256, 2)])
+def test_tuning_does_not_change_results(wg, G):
+    R = _R()
+    probs = [R.Problem(L=8, n_windows=3, walkers_per_window=5, k_final=10, interval=700, seed=s)
+             for s in range(7)]
+    _say(f"case: tuning wg={wg} G={G}")
+    plan = R.Plan(probs, R.Tuning(walkers_per_wg=wg, graph_intervals=G))
+    plan.init()
+    plan.run(25)
+    for i, p in enumerate(probs):
+        o = _oracle_of(p)
+        o.run(25)
+        compare(plan, i, o)
+
+
+def test_odd_interval_split_calls_and_boundaries():
+    R = _R()
+    p = R.Problem(L=6, n_windows=2, overlap=(1, 2), walkers_per_window=3, k_final=6, interval=333, seed=77)
+    _say("case: odd trial counts, split sweep/reduce/exchange calls")
+    plan = R.Plan([p])
+    plan.init()
+    orc = _oracle_of(p)
+    for n in (1, 2, 3, 333, 1000, 7):
+        plan.sweep(n)
+        orc.sweep(n)
+        compare(plan, 0, orc)
+        plan.reduce_lnf()
+        plan.exchange()
+        orc.boundary()
+        compare(plan, 0, orc)
+    plan.sweep(0)
+    compare(plan, 0, orc)
+
+
+def test_l64_rows_of_two_words():
+    R = _R()
+    p = R.Problem(L=64, n_windows=4, walkers_per_window=2, k_final=20, interval=4000, seed=3)
+    _say("case: 64x64, 4 windows x 2, 3 intervals")
+    plan = R.Plan([p])
+    plan.init()
+    orc = _oracle_of(p)
+    compare(plan, 0, orc, tables=False)
+    plan.run(3)
+    orc.run(3)
+    compare(plan, 0, orc)
+
+
+def test_init_all_up_entry_walks():
+    R = _R()
+    p = R.Problem(L=12, n_windows=6, walkers_per_window=2, k_final=10, interval=500, seed=21, init=1)
+    _say("case: all-up start, entry walk into 6 windows")
+    plan = R.Plan([p])
+    plan.init()
+    orc = _oracle_of(p)
+    compare(plan, 0, orc)
+    plan.run(4)
+    orc.run(4)
+    compare(plan, 0, orc)

@@ -80,7 +80,8 @@ typedef struct {
     int32_t walkers_per_wg;   /* 64, 128 or 256 lanes (= walkers) per workgroup; 0 = auto */
     int32_t graph_intervals;  /* intervals captured per graph (batched); 0 = auto */
     int32_t grid_waves_per_cu;/* persistent grid size in waves per CU; 0 = one tile per workgroup */
-    int32_t reserved[4];      /* must be 0 */
+    int32_t profile;          /* 1: start with profiling on (see rewl_set_profile) */
+    int32_t reserved[3];      /* must be 0 */
 } rewl_tuning;
 
 /* Buffers the caller provides (device memory). */
@@ -165,6 +166,14 @@ rewl_status rewl_lnz_backward(const double* lng, int32_t N, int32_t e0, int32_t 
                               int64_t G, const double* lnz, const double* grad_out,
                               double* grad_beta, double* grad_h, double* grad_lng,
                               double* mom, int32_t order, void* hip_stream);
+
+/* Profiling of the batched form: while on, rewl_run enqueues its intervals
+ * one launch at a time (not from the graph) with a HIP event pair around
+ * every sweep kernel; rewl_sweep_times then gives those kernels' durations
+ * (ms) for the most recent rewl_run, in launch order, writing min(cap, count)
+ * values and the count, and synchronises.  Results are unchanged. */
+rewl_status rewl_set_profile(rewl_plan* plan, int32_t on);
+rewl_status rewl_sweep_times(rewl_plan* plan, float* ms, int32_t cap, int32_t* count);
 
 const char* rewl_last_error(void);
 

@@ -41,7 +41,7 @@ class _Problem(C.Structure):
 
 class _Tuning(C.Structure):
     _fields_ = [("form", C.c_int32), ("walkers_per_wg", C.c_int32), ("graph_intervals", C.c_int32),
-                ("grid_waves_per_cu", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("grid_waves_per_cu", C.c_int32), ("profile", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 _lib = None
@@ -75,6 +75,8 @@ def lib():
                                   P, P], C.c_int),
             "rewl_lnz_backward": ([P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_int64,
                                    P, P, P, P, P, P, C.c_int32, P], C.c_int),
+            "rewl_sweep_times": ([P, P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+            "rewl_set_profile": ([P, C.c_int32], C.c_int),
             "rewl_last_error": ([], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -119,10 +121,11 @@ class Tuning:
     walkers_per_wg: int = 0
     graph_intervals: int = 0
     grid_waves_per_cu: int = 0
+    profile: int = 0
 
     def _c(self):
         return _Tuning(self.form, self.walkers_per_wg, self.graph_intervals, self.grid_waves_per_cu,
-                       (C.c_int32 * 4)(0, 0, 0, 0))
+                       self.profile, (C.c_int32 * 3)(0, 0, 0))
 
 
 class Plan:
@@ -183,6 +186,17 @@ class Plan:
         tr = np.zeros(n, np.int64)
         _check(lib().rewl_query(self._h, st.ctypes.data, dn.ctypes.data, tr.ctypes.data))
         return {"stage": st, "done": dn.astype(bool), "trials": tr}
+
+    def set_profile(self, on):
+        _check(lib().rewl_set_profile(self._h, 1 if on else 0))
+
+    def sweep_times(self):
+        """Durations (ms) of the sweep kernels of the last profiled rewl_run."""
+        cap = 4096
+        buf = np.zeros(cap, np.float32)
+        n = C.c_int32()
+        _check(lib().rewl_sweep_times(self._h, buf.ctypes.data, cap, C.byref(n)))
+        return buf[:min(cap, n.value)].astype(np.float64)
 
     def window(self, prob, w):
         lo, hi = C.c_int32(), C.c_int32()

@@ -65,6 +65,9 @@ struct rewl_plan {
     DevState S{};
     hipGraphExec_t graph = nullptr;
     int graph_g = 0;
+    std::vector<hipEvent_t> ev;  // profile: [2i] before, [2i+1] after sweep i of the last run
+    int ev_used = 0;
+    bool profile = false;
 };
 
 namespace {
@@ -140,10 +143,19 @@ DevState make_state(rewl_plan* P) {
     return S;
 }
 
-int wg_of(const rewl_plan* P) { return P->tune.walkers_per_wg > 0 ? P->tune.walkers_per_wg : 64; }
+// Workgroup size: a tuned value, else 256 lanes once the batch fills the chip
+// several times over, 64 below that (fewer, fuller waves per CU).
+int wg_of(const rewl_plan* P) {
+    if (P->tune.walkers_per_wg > 0) return P->tune.walkers_per_wg;
+    return P->n_walk >= (1 << 17) ? 256 : 64;
+}
 
-rewl_status enqueue_sweep(rewl_plan* P, int64_t n) {
+int graph_len(const rewl_plan* P) { return P->tune.graph_intervals > 0 ? P->tune.graph_intervals : 8; }
+
+rewl_status enqueue_sweep(rewl_plan* P, int64_t n, int ev_slot = -1) {
+    if (ev_slot >= 0) HIPCHK(P, hipEventRecord(P->ev[2 * ev_slot], P->stream), "event record");
     HIPCHK(P, launch_sweep(P->S, 0, P->n_walk, n, P->l_max, wg_of(P), P->stream), "sweep launch");
+    if (ev_slot >= 0) HIPCHK(P, hipEventRecord(P->ev[2 * ev_slot + 1], P->stream), "event record");
     return REWL_OK;
 }
 
@@ -158,8 +170,8 @@ rewl_status enqueue_exchange(rewl_plan* P) {
     return REWL_OK;
 }
 
-rewl_status enqueue_interval_batched(rewl_plan* P) {
-    rewl_status s = enqueue_sweep(P, P->interval);
+rewl_status enqueue_interval_batched(rewl_plan* P, int ev_slot = -1) {
+    rewl_status s = enqueue_sweep(P, P->interval, ev_slot);
     if (s != REWL_OK) return s;
     s = enqueue_boundary(P);
     if (s != REWL_OK) return s;
@@ -304,6 +316,8 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
             return fail(REWL_EINVAL, "walkers_per_wg must be 0, 64, 128 or 256");
         if (tn.graph_intervals < 0 || tn.graph_intervals > 4096) return fail(REWL_EINVAL, "graph_intervals 0..4096");
         if (tn.grid_waves_per_cu < 0) return fail(REWL_EINVAL, "grid_waves_per_cu must be >= 0");
+        if (tn.profile != 0 && tn.profile != 1) return fail(REWL_EINVAL, "profile must be 0 or 1");
+        if (tn.profile && tn.form != REWL_FORM_BATCHED) return fail(REWL_EINVAL, "profiling times the batched form");
         for (int r : tn.reserved)
             if (r != 0) return fail(REWL_EINVAL, "tuning.reserved must be 0");
     }
@@ -315,6 +329,7 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
     if (!P) return fail(REWL_ENOMEM, "plan allocation");
     P->probs.assign(problems, problems + n_problems);
     P->tune = tn;
+    P->profile = tn.profile != 0;
     P->interval = X;
     int64_t walker = 0;
     uint64_t bins = 0, words = 0;
@@ -404,6 +419,7 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
 void rewl_plan_destroy(rewl_plan* P) {
     if (!P) return;
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
+    for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     delete P;
 }
 
@@ -480,6 +496,10 @@ rewl_status rewl_init(rewl_plan* P) {
         if (spent >= cap_total) return fail(REWL_ESTATE, "entry walk exceeded 2^40 trials");
     }
     P->initialised = true;
+    if (P->tune.form == REWL_FORM_BATCHED) {
+        // capture the interval graph now, so the first rewl_run does not pay for it
+        if ((s = ensure_graph(P, graph_len(P))) != REWL_OK) return s;
+    }
     return REWL_OK;
 }
 
@@ -523,7 +543,21 @@ rewl_status rewl_run(rewl_plan* P, int64_t n) {
             if ((s = run_interval_plain(P)) != REWL_OK) return s;
         return REWL_OK;
     }
-    const int G = P->tune.graph_intervals > 0 ? P->tune.graph_intervals : 8;
+    if (P->profile) {
+        // eager launches with an event pair around every sweep kernel
+        while (P->ev.size() < 2 * static_cast<size_t>(n)) {
+            hipEvent_t e;
+            HIPCHK(P, hipEventCreate(&e), "event create");
+            P->ev.push_back(e);
+        }
+        P->ev_used = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            if ((s = enqueue_interval_batched(P, static_cast<int>(i))) != REWL_OK) return s;
+            P->ev_used = static_cast<int>(i + 1);
+        }
+        return REWL_OK;
+    }
+    const int G = graph_len(P);
     int64_t i = 0;
     if (n >= G) {
         if ((s = ensure_graph(P, G)) != REWL_OK) return s;
@@ -635,3 +669,23 @@ rewl_status rewl_lnz_backward(const double* lng, int32_t N, int32_t e0, int32_t 
 }
 
 }  // extern "C"
+
+extern "C" rewl_status rewl_set_profile(rewl_plan* P, int32_t on) {
+    if (!P) return fail(REWL_EINVAL, "null plan");
+    if (on != 0 && on != 1) return fail(REWL_EINVAL, "on must be 0 or 1");
+    if (on && P->tune.form != REWL_FORM_BATCHED) return fail(REWL_EINVAL, "profiling times the batched form");
+    P->profile = on != 0;
+    return REWL_OK;
+}
+
+extern "C" rewl_status rewl_sweep_times(rewl_plan* P, float* ms, int32_t cap, int32_t* count) {
+    rewl_status s = usable(P);
+    if (s != REWL_OK) return s;
+    if (!ms || !count || cap < 0) return fail(REWL_EINVAL, "null argument");
+    if (!P->profile || P->ev_used == 0) return fail(REWL_ESTATE, "no profiled rewl_run yet");
+    HIPCHK(P, hipStreamSynchronize(P->stream), "timing sync");
+    for (int i = 0; i < P->ev_used && i < cap; ++i)
+        HIPCHK(P, hipEventElapsedTime(&ms[i], P->ev[2 * i], P->ev[2 * i + 1]), "event time");
+    *count = P->ev_used;
+    return REWL_OK;
+}

@@ -66,6 +66,8 @@ def main():
     ap.add_argument("--cpu-intervals", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--wg", type=int, default=0, help="walkers per workgroup (0 = library's choice)")
+    ap.add_argument("--grid-waves", type=int, default=0, help="persistent grid waves per CU (0 = library's choice)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -94,7 +96,8 @@ def main():
 
     # ---------------- batched form on the replica batch (the headline value)
     log(f"[bench] batched: {args.replicas} replicas of the 16x16 REWL problem, init ...")
-    plan = R.Plan(problems(args.replicas, R), R.Tuning(graph_intervals=K), device=dev)
+    tuning = R.Tuning(graph_intervals=K, walkers_per_wg=args.wg, grid_waves_per_cu=args.grid_waves)
+    plan = R.Plan(problems(args.replicas, R), tuning, device=dev)
     t0 = time.perf_counter()
     plan.init()
     log(f"[bench] init + window entry {time.perf_counter() - t0:.2f}s; warmup {W}, timed {K} steps")

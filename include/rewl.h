@@ -79,7 +79,8 @@ typedef struct {
                                  round trip per interval */
     int32_t walkers_per_wg;   /* 64, 128 or 256 lanes (= walkers) per workgroup; 0 = auto */
     int32_t graph_intervals;  /* intervals captured per graph (batched); 0 = auto */
-    int32_t grid_waves_per_cu;/* persistent grid size in waves per CU; 0 = one tile per workgroup */
+    int32_t grid_waves_per_cu;/* persistent grid: at most this many wavefronts per CU, each
+                                 running its tiles of walkers in turn; 0 = auto */
     int32_t profile;          /* 1: start with profiling on (see rewl_set_profile) */
     int32_t reserved[3];      /* must be 0 */
 } rewl_tuning;

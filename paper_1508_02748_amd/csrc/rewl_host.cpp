@@ -55,7 +55,7 @@ struct rewl_plan {
     // STATE buffer offsets
     size_t off_wd = 0, off_pd = 0, off_pairs = 0, off_e = 0, off_m = 0, off_t = 0, off_te = 0,
            off_nseen = 0, off_flag = 0, off_scan = 0, off_stage = 0, off_done = 0, off_rnd = 0,
-           off_tstage = 0, off_xr = 0, off_xon = 0, off_lngb = 0, off_tseen = 0, off_cnt = 0;
+           off_tstage = 0, off_xr = 0, off_xon = 0, off_adv = 0, off_lngb = 0, off_tseen = 0, off_cnt = 0;
     // binding
     bool bound = false;
     bool broken = false;
@@ -68,6 +68,7 @@ struct rewl_plan {
     std::vector<hipEvent_t> ev;  // profile: [2i] before, [2i+1] after sweep i of the last run
     int ev_used = 0;
     bool profile = false;
+    int n_cu = 256;
 };
 
 namespace {
@@ -119,7 +120,8 @@ DevState make_state(rewl_plan* P) {
     S.wd = reinterpret_cast<const WDesc*>(st + P->off_wd);
     S.pd = reinterpret_cast<const PDesc*>(st + P->off_pd);
     S.pairs = reinterpret_cast<const PairDesc*>(st + P->off_pairs);
-    S.tables = static_cast<Bin*>(P->buf[REWL_BUF_TABLES]);
+    S.lng = static_cast<int64_t*>(P->buf[REWL_BUF_TABLES]);
+    S.snap = S.lng + P->n_bins;
     S.spins = static_cast<uint32_t*>(P->buf[REWL_BUF_SPINS]);
     S.e = reinterpret_cast<int32_t*>(st + P->off_e);
     S.m = reinterpret_cast<int32_t*>(st + P->off_m);
@@ -134,6 +136,7 @@ DevState make_state(rewl_plan* P) {
     S.tstage = reinterpret_cast<int64_t*>(st + P->off_tstage);
     S.xr = reinterpret_cast<int64_t*>(st + P->off_xr);
     S.xon = reinterpret_cast<int32_t*>(st + P->off_xon);
+    S.adv = reinterpret_cast<int32_t*>(st + P->off_adv);
     S.lngb = reinterpret_cast<int64_t*>(st + P->off_lngb);
     S.tseen = reinterpret_cast<int64_t*>(st + P->off_tseen);
     S.counters = reinterpret_cast<int32_t*>(st + P->off_cnt);
@@ -152,9 +155,24 @@ int wg_of(const rewl_plan* P) {
 
 int graph_len(const rewl_plan* P) { return P->tune.graph_intervals > 0 ? P->tune.graph_intervals : 8; }
 
+// Persistent grid: at most grid_waves_per_cu wavefronts per CU in flight.
+// Automatic choice: once the batch has at least twice that many walkers, one
+// wavefront per SIMD (4 per CU) -- more walkers in flight evict each other's
+// table lines from the L2 faster than they hide latency.
+int max_grid_of(const rewl_plan* P) {
+    int gw = P->tune.grid_waves_per_cu;
+    if (gw <= 0) {
+        const long long one_per_simd = 4ll * P->n_cu * 64;
+        if (P->n_walk < 2 * one_per_simd) return 0;
+        gw = 4;
+    }
+    const long long lanes = static_cast<long long>(gw) * P->n_cu * 64;
+    return static_cast<int>(std::max<long long>(1, lanes / wg_of(P)));
+}
+
 rewl_status enqueue_sweep(rewl_plan* P, int64_t n, int ev_slot = -1) {
     if (ev_slot >= 0) HIPCHK(P, hipEventRecord(P->ev[2 * ev_slot], P->stream), "event record");
-    HIPCHK(P, launch_sweep(P->S, 0, P->n_walk, n, P->l_max, wg_of(P), P->stream), "sweep launch");
+    HIPCHK(P, launch_sweep(P->S, 0, P->n_walk, n, P->l_max, wg_of(P), max_grid_of(P), P->stream), "sweep launch");
     if (ev_slot >= 0) HIPCHK(P, hipEventRecord(P->ev[2 * ev_slot + 1], P->stream), "event record");
     return REWL_OK;
 }
@@ -162,6 +180,7 @@ rewl_status enqueue_sweep(rewl_plan* P, int64_t n, int ev_slot = -1) {
 rewl_status enqueue_boundary(rewl_plan* P) {
     HIPCHK(P, launch_flat(P->S, P->stream), "flatness launch");
     HIPCHK(P, launch_stage(P->S, P->stream), "stage launch");
+    HIPCHK(P, launch_snapshot(P->S, P->stream), "snapshot launch");
     return REWL_OK;
 }
 
@@ -204,12 +223,12 @@ rewl_status run_interval_plain(rewl_plan* P) {
         const PDesc& q = P->pd[p];
         for (int w = 0; w < q.nwin; ++w) {
             HIPCHK(P, launch_sweep(P->S, q.walker_off + static_cast<int64_t>(w) * q.W, q.W, P->interval,
-                                   q.L, wg, P->stream), "plain sweep launch");
+                                   q.L, wg, 0, P->stream), "plain sweep launch");
         }
     }
     HIPCHK(P, launch_flat(P->S, P->stream), "flatness launch");
     const size_t np = P->pd.size();
-    std::vector<int32_t> stage, done, xon;
+    std::vector<int32_t> stage, done, xon, adv;
     std::vector<int64_t> rnd, tstage, xr, t, lngb, tseen;
     std::vector<uint32_t> flag;
     rewl_status s;
@@ -221,6 +240,7 @@ rewl_status run_interval_plain(rewl_plan* P) {
         return s;
     HIPCHK(P, hipStreamSynchronize(P->stream), "plain boundary sync");
     bool overflow = false;
+    adv.assign(np, 0);
     for (size_t p = 0; p < np; ++p) {
         const PDesc& q = P->pd[p];
         if (done[p]) {
@@ -247,6 +267,7 @@ rewl_status run_interval_plain(rewl_plan* P) {
             }
             stage[p] += 1;
             tstage[p] = tnow;
+            adv[p] = 1;
             for (int i = 0; i < nw; ++i) flag[q.walker_off + i] = 0;
         }
         xr[p] = r;
@@ -255,8 +276,10 @@ rewl_status run_interval_plain(rewl_plan* P) {
     }
     if ((s = h2d(P, stage, P->off_stage)) || (s = h2d(P, done, P->off_done)) || (s = h2d(P, rnd, P->off_rnd)) ||
         (s = h2d(P, tstage, P->off_tstage)) || (s = h2d(P, xr, P->off_xr)) || (s = h2d(P, xon, P->off_xon)) ||
-        (s = h2d(P, lngb, P->off_lngb)) || (s = h2d(P, tseen, P->off_tseen)) || (s = h2d(P, flag, P->off_flag)))
+        (s = h2d(P, lngb, P->off_lngb)) || (s = h2d(P, tseen, P->off_tseen)) || (s = h2d(P, flag, P->off_flag)) ||
+        (s = h2d(P, adv, P->off_adv)))
         return s;
+    HIPCHK(P, launch_snapshot(P->S, P->stream), "snapshot launch");
     if (overflow) {
         std::vector<int32_t> cnt;
         if ((s = d2h(P, cnt, P->off_cnt, 4))) return s;
@@ -365,8 +388,10 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
                 wd.hi = hi;
                 wd.win = w;
                 wd.gid = w * q.walkers_per_window + a;
+                wd.ntm = static_cast<uint32_t>((d.N + 1 + TILE_M - 1) / TILE_M);
+                wd.nbins = static_cast<uint32_t>((hi - lo + 1 + TILE_E - 1) / TILE_E) * wd.ntm * TILE_BINS;
                 P->wd.push_back(wd);
-                bins += static_cast<uint64_t>(hi - lo + 1) * (d.N + 1);
+                bins += wd.nbins;
                 words += static_cast<uint64_t>(q.L) * d.row_words;
                 ++walker;
             }
@@ -406,10 +431,11 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
     P->off_tstage = take(np * 8);
     P->off_xr = take(np * 8);
     P->off_xon = take(np * 4);
+    P->off_adv = take(np * 4);
     P->off_lngb = take(np * 8);
     P->off_tseen = take(np * 8);
     P->off_cnt = take(16);
-    P->sizes[REWL_BUF_TABLES] = align_up(bins * sizeof(Bin), A);
+    P->sizes[REWL_BUF_TABLES] = align_up(2 * bins * sizeof(int64_t), A);
     P->sizes[REWL_BUF_SPINS] = align_up(words * 4, A);
     P->sizes[REWL_BUF_STATE] = o;
     *out = P;
@@ -461,6 +487,12 @@ rewl_status rewl_plan_bind(rewl_plan* P, void* const* dev_ptrs, void* hip_stream
     }
     P->S = make_state(P);
     HIPCHK(P, sweep_setup(), "kernel attributes");
+    {
+        int dev = 0, ncu = 0;
+        HIPCHK(P, hipGetDevice(&dev), "device query");
+        HIPCHK(P, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "device query");
+        if (ncu > 0) P->n_cu = ncu;
+    }
     char* st = static_cast<char*>(P->buf[REWL_BUF_STATE]);
     HIPCHK(P, hipMemcpyAsync(st + P->off_wd, P->wd.data(), P->wd.size() * sizeof(WDesc), hipMemcpyHostToDevice,
                              P->stream), "descriptor upload");
@@ -512,7 +544,7 @@ rewl_status rewl_sweep(rewl_plan* P, int64_t n) {
         const int wg = wg_of(P);
         for (const PDesc& q : P->pd)
             for (int w = 0; w < q.nwin; ++w)
-                HIPCHK(P, launch_sweep(P->S, q.walker_off + static_cast<int64_t>(w) * q.W, q.W, n, q.L, wg,
+                HIPCHK(P, launch_sweep(P->S, q.walker_off + static_cast<int64_t>(w) * q.W, q.W, n, q.L, wg, 0,
                                        P->stream), "plain sweep launch");
         return REWL_OK;
     }
@@ -596,16 +628,20 @@ rewl_status rewl_read_walker(rewl_plan* P, int32_t prob, int32_t w, int32_t a, i
     if (w < 0 || w >= q.nwin || a < 0 || a >= q.W) return fail(REWL_EINVAL, "walker out of range");
     const int64_t g = q.walker_off + static_cast<int64_t>(w) * q.W + a;
     const WDesc& d = P->wd[g];
-    const size_t nb = static_cast<size_t>(d.hi - d.lo + 1) * (q.N + 1);
+    const int nE = d.hi - d.lo + 1, nM = q.N + 1;
+    const size_t nb = static_cast<size_t>(nE) * nM;
     if ((lng || H) && cap_bins < nb) return fail(REWL_EINVAL, "cap_bins too small");
-    std::vector<Bin> bins;
+    std::vector<int64_t> tl, ts;
     std::vector<uint32_t> words;
     std::vector<int32_t> ev, mv, stage;
     std::vector<int64_t> tv;
     if (lng || H) {
-        bins.resize(nb);
-        HIPCHK(P, hipMemcpyAsync(bins.data(), static_cast<Bin*>(P->buf[REWL_BUF_TABLES]) + d.table_off,
-                                 nb * sizeof(Bin), hipMemcpyDeviceToHost, P->stream), "table read");
+        tl.resize(d.nbins);
+        ts.resize(d.nbins);
+        HIPCHK(P, hipMemcpyAsync(tl.data(), P->S.lng + d.table_off, d.nbins * sizeof(int64_t),
+                                 hipMemcpyDeviceToHost, P->stream), "table read");
+        HIPCHK(P, hipMemcpyAsync(ts.data(), P->S.snap + d.table_off, d.nbins * sizeof(int64_t),
+                                 hipMemcpyDeviceToHost, P->stream), "table read");
     }
     const size_t nwords = static_cast<size_t>(q.L) * q.row_words;
     if (spins) {
@@ -617,11 +653,15 @@ rewl_status rewl_read_walker(rewl_plan* P, int32_t prob, int32_t w, int32_t a, i
         (s = d2h(P, tv, P->off_t, P->n_walk)) || (s = d2h(P, stage, P->off_stage, P->pd.size())))
         return s;
     HIPCHK(P, hipStreamSynchronize(P->stream), "walker read sync");
-    const uint64_t st = static_cast<uint64_t>(stage[prob]);
-    for (size_t i = 0; i < nb && (lng || H); ++i) {
-        if (lng) lng[i] = bins[i].lng;
-        if (H) H[i] = ((bins[i].hs & STAMP_MASK) == st) ? (bins[i].hs >> STAMP_BITS) : 0;
-    }
+    const int sh = q.K - stage[prob];
+    if (lng || H)
+        for (int er = 0; er < nE; ++er)
+            for (int mm = 0; mm < nM; ++mm) {
+                const uint32_t ti = tile_index(er, mm, d.ntm);
+                const size_t oi = static_cast<size_t>(er) * nM + mm;
+                if (lng) lng[oi] = tl[ti];
+                if (H) H[oi] = static_cast<uint64_t>(tl[ti] - ts[ti]) >> sh;
+            }
     if (spins)
         for (int r = 0; r < q.L; ++r)
             for (int c = 0; c < q.L; ++c)

@@ -6,26 +6,34 @@
 
 namespace rewl {
 
-// One (walker, e, m) cell of a window table: ln g in units of 2^-K, and the
-// visit count H of stage `stamp` packed as (H << 6) | stamp.  A count written
-// in an earlier stage reads as zero, so resetting H at a stage change costs
-// nothing.  ln g > 0 marks a bin the walker has visited (ln g only grows).
-struct Bin {
-    int64_t lng;
-    uint64_t hs;
-};
-static_assert(sizeof(Bin) == 16, "bin layout");
-constexpr int STAMP_BITS = 6;
-constexpr uint64_t STAMP_MASK = (1u << STAMP_BITS) - 1;
+// Window tables.  Each walker owns two int64 tables over its window rows
+// e in [lo, hi] and all m in [0, N]: ln g in units of 2^-K (> 0 marks a bin
+// the walker has visited; ln g only grows), and a snapshot of ln g taken when
+// the current stage began.  Every visit in stage s adds 2^(K-s), so the visit
+// count of the stage is H = (ln g - snapshot) >> (K - s): a trial touches only
+// ln g, and resetting H at a stage change is one copy of the table.
+//
+// Both tables are stored in tiles of 4 energy rows x 4 magnetization columns
+// (16 bins = 128 bytes, one cache line), tiles row-major: a walker's trial
+// bins (e-2..e+2, m-1 / m+1) fall into about two lines instead of five.
+constexpr int TILE_E = 4, TILE_M = 4, TILE_BINS = TILE_E * TILE_M;
+
+__host__ __device__ inline uint32_t tile_index(int er, int m, uint32_t ntm) {
+    return ((static_cast<uint32_t>(er >> 2) * ntm + static_cast<uint32_t>(m >> 2)) << 4) |
+           (static_cast<uint32_t>(er & 3) << 2) | static_cast<uint32_t>(m & 3);
+}
 
 // Static description of one walker.
 struct WDesc {
-    uint64_t table_off;  // first bin of its (hi-lo+1) x (N+1) table
+    uint64_t table_off;  // first bin of its tiled table (ln g; the snapshot sits at the same
+                         // offset of the snapshot table)
     uint32_t spin_off;   // first word of its L x row_words packed spins
     int32_t prob;        // problem index
     int32_t lo, hi;      // energy-bin window
     int32_t win;         // window index within the problem
     int32_t gid;         // walker id within the problem: win * W + a
+    uint32_t ntm;        // tiles per energy row = ceil((N + 1) / 4)
+    uint32_t nbins;      // bins of its tiled table = ceil((hi - lo + 1) / 4) * ntm * 16
 };
 
 // Static description of one problem.
@@ -47,7 +55,8 @@ struct DevState {
     const WDesc* wd;
     const PDesc* pd;
     const PairDesc* pairs;
-    Bin* tables;
+    int64_t* lng;     // ln g tables
+    int64_t* snap;    // ln g at the start of the current stage
     uint32_t* spins;
     // per walker
     int32_t* e;
@@ -64,6 +73,7 @@ struct DevState {
     int64_t* tstage;  // trial count at the start of the stage
     int64_t* xr;      // exchange round of the boundary just closed
     int32_t* xon;     // that boundary exchanges
+    int32_t* adv;     // the problem moved to the next stage at the boundary just closed
     int64_t* lngb;    // upper bound of any ln g entry (units), for the int64 headroom guard
     int64_t* tseen;   // trial count at the last boundary
     // misc
@@ -80,10 +90,11 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_init(const DevState& S, hipStream_t st);
 hipError_t launch_entry(const DevState& S, int64_t cap, hipStream_t st);
 hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int64_t n_trials,
-                        int l_max, int wg, hipStream_t st);
+                        int l_max, int wg, int max_grid, hipStream_t st);
 hipError_t sweep_setup();
 hipError_t launch_flat(const DevState& S, hipStream_t st);
 hipError_t launch_stage(const DevState& S, hipStream_t st);
+hipError_t launch_snapshot(const DevState& S, hipStream_t st);
 hipError_t launch_exchange(const DevState& S, hipStream_t st);
 
 // Reweighting.

@@ -170,6 +170,7 @@ __global__ void k_init(DevState S) {
         S.xon[p] = 0;
         S.lngb[p] = 0;
         S.tseen[p] = 0;
+        S.adv[p] = 0;
     }
 }
 
@@ -226,20 +227,60 @@ __global__ void k_entry(DevState S, int64_t cap) {
 }
 
 // ------------------------------------------------------------------ sweep
-// n_trials Wang-Landau trials (Eq. 1) for each walker g in
-// [g_begin, g_begin + g_count) of an unfinished problem.  Each lane owns one
-// walker; its spins sit in LDS column `lane`.  No lane touches another's data,
-// so the kernel has no barriers.
+// Acceptance decision identical to accept_move, reached faster: a single
+// precision estimate a of exp(x) (hardware exp2, relative error below 5e-6
+// for -23 < x < 0 including the rounding of x and u to float) decides unless
+// u lies within 1e-4 relative of a; only then is the double-precision
+// exp_neg evaluated.  Both branches give u < exp_neg(x) exactly.
+__device__ __forceinline__ bool accept_fast(int64_t delta, uint32_t u_word, int K) {
+    if (delta >= 0) return true;
+    if (delta <= -(static_cast<int64_t>(23) << K)) return false;
+    const double x = ldexp(static_cast<double>(delta), -K);
+    const double u = __dmul_rn(__dadd_rn(static_cast<double>(u_word), 0.5), 1.0 / 4294967296.0);
+    const float a = __builtin_amdgcn_exp2f(static_cast<float>(x) * 1.44269504f);
+    const float uf = static_cast<float>(u);
+    if (uf < a * 0.9999f) return true;
+    if (uf > a * 1.0001f) return false;
+    return u < exp_neg(x);
+}
+
+// First and second halves of a Philox4x32-10 evaluation, so that the next
+// block's rounds can run while the current trials wait for their gathers.
+struct PhiloxRun {
+    uint32_t c0, c1, c2, c3, k0, k1;
+};
+
+__device__ __forceinline__ PhiloxRun philox_start(uint64_t key, uint64_t block, uint32_t walker) {
+    return {static_cast<uint32_t>(block), static_cast<uint32_t>(block >> 32), walker, TAG_WL << 24,
+            static_cast<uint32_t>(key), static_cast<uint32_t>(key >> 32)};
+}
+
+template <int NR>
+__device__ __forceinline__ void philox_rounds(PhiloxRun& q) {
+#pragma unroll
+    for (int round = 0; round < NR; ++round) {
+        const uint32_t a_lo = 0xD2511F53u * q.c0;
+        const uint32_t a_hi = __umulhi(0xD2511F53u, q.c0);
+        const uint32_t b_lo = 0xCD9E8D57u * q.c2;
+        const uint32_t b_hi = __umulhi(0xCD9E8D57u, q.c2);
+        const uint32_t n0 = b_hi ^ q.c1 ^ q.k0;
+        const uint32_t n2 = a_hi ^ q.c3 ^ q.k1;
+        q.c0 = n0;
+        q.c1 = b_lo;
+        q.c2 = n2;
+        q.c3 = a_lo;
+        q.k0 += 0x9E3779B9u;
+        q.k1 += 0xBB67AE85u;
+    }
+}
+
+// n_trials Wang-Landau trials (Eq. 1) for walker g (lane `lane` of a
+// workgroup of WG lanes).  Its spins sit in LDS column `lane`; no lane touches
+// another's data, so there are no barriers.  The bin the walker occupies is
+// held in registers and written back when the walker leaves it.
 template <typename RowT>
-__global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int64_t g_count,
-                                               int64_t n_trials) {
-    extern __shared__ unsigned char lds_raw[];
-    RowT* lds = reinterpret_cast<RowT*>(lds_raw);
-    const int lane = threadIdx.x;
-    const int WG = blockDim.x;
-    const int64_t gi = static_cast<int64_t>(blockIdx.x) * WG + lane;
-    if (gi >= g_count) return;
-    const int64_t g = g_begin + gi;
+__device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int lane, int WG, int64_t g,
+                                             int64_t n_trials) {
     const WDesc d = S.wd[g];
     const int p = d.prob;
     if (S.done[p]) return;
@@ -248,10 +289,10 @@ __global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int6
     const int s = S.stage[p];
     const int64_t inc = static_cast<int64_t>(1) << (K - s);
     const int lo = d.lo, hi = d.hi;
-    const uint64_t stride = static_cast<uint64_t>(P.N) + 1;
+    const uint32_t ntm = d.ntm;
     const uint64_t seed = P.seed;
     const uint32_t gid = static_cast<uint32_t>(d.gid);
-    Bin* tab = S.tables + d.table_off;
+    int64_t* tab = S.lng + d.table_off;
 
     const uint32_t* gsp = S.spins + d.spin_off;
     for (int r = 0; r < L; ++r) {
@@ -265,19 +306,11 @@ __global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int6
     int e = S.e[g], m = S.m[g];
     int64_t t = S.t[g];
     uint32_t nseen = S.nseen[g];
-    uint64_t cur = static_cast<uint64_t>(e - lo) * stride + static_cast<uint64_t>(m);
-    Bin cb = tab[cur];
-    int64_t lng_cur = cb.lng;
-    uint64_t h_cur = ((cb.hs & STAMP_MASK) == static_cast<uint64_t>(s)) ? (cb.hs >> STAMP_BITS) : 0;
+    uint32_t cur = tile_index(e - lo, m, ntm);
+    int64_t lng_cur = tab[cur];
 
-    Words4 blk = {0, 0, 0, 0};
-    for (int64_t i = 0; i < n_trials; ++i) {
-        if (i == 0 || (t & 1) == 0) {
-            const uint64_t b = static_cast<uint64_t>(t) >> 1;
-            blk = philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid, TAG_WL << 24);
-        }
-        const uint32_t sw = (t & 1) ? blk.z : blk.x;
-        const uint32_t uw = (t & 1) ? blk.w : blk.y;
+    // One trial with the words (sw, uw) of its Philox block.
+    auto trial = [&](uint32_t sw, uint32_t uw) {
         int r, c;
         site_rc(sw, L, r, c);
         const int ru = r == 0 ? L - 1 : r - 1;
@@ -293,27 +326,53 @@ __global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int6
                            ((static_cast<uint32_t>(row >> cr) & 1u) ^ bc) +
                            ((static_cast<uint32_t>(rowu >> c) & 1u) ^ bc) +
                            ((static_cast<uint32_t>(rowd >> c) & 1u) ^ bc);
-        const int e2 = e + 2 - static_cast<int>(k);    // dE = 8 - 4k
+        const int e2 = e + 2 - static_cast<int>(k);       // dE = 8 - 4k
         const int m2 = m + 1 - 2 * static_cast<int>(bc);  // dM = -2 s
-        if (e2 >= lo && e2 <= hi) {
-            const uint64_t idx2 = static_cast<uint64_t>(e2 - lo) * stride + static_cast<uint64_t>(m2);
-            const Bin tb = tab[idx2];
-            if (accept_move(lng_cur - tb.lng, uw, K)) {
-                tab[cur] = Bin{lng_cur, (h_cur << STAMP_BITS) | static_cast<uint64_t>(s)};
-                lds[r * WG + lane] = row ^ (static_cast<RowT>(1) << c);
-                e = e2;
-                m = m2;
-                cur = idx2;
-                lng_cur = tb.lng;
-                h_cur = ((tb.hs & STAMP_MASK) == static_cast<uint64_t>(s)) ? (tb.hs >> STAMP_BITS) : 0;
-            }
+        const bool in = e2 >= lo && e2 <= hi;
+        // gather unconditionally (a bin of the current row when out of the window)
+        const uint32_t idx2 = tile_index((in ? e2 : e) - lo, m2, ntm);
+        const int64_t lng2 = tab[idx2];
+        if (in && accept_fast(lng_cur - lng2, uw, K)) {
+            tab[cur] = lng_cur;
+            lds[r * WG + lane] = row ^ (static_cast<RowT>(1) << c);
+            e = e2;
+            m = m2;
+            cur = idx2;
+            lng_cur = lng2;
         }
         nseen += (lng_cur == 0) ? 1u : 0u;
         lng_cur += inc;
-        h_cur += 1;
         ++t;
+    };
+
+    int64_t i = 0;
+    Words4 blk = {0, 0, 0, 0};
+    if (n_trials > 0 && (t & 1)) {  // odd start: second half of the current block
+        const uint64_t b = static_cast<uint64_t>(t) >> 1;
+        blk = philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid, TAG_WL << 24);
+        trial(blk.z, blk.w);
+        ++i;
     }
-    tab[cur] = Bin{lng_cur, (h_cur << STAMP_BITS) | static_cast<uint64_t>(s)};
+    if (i + 2 <= n_trials) {
+        const uint64_t b = static_cast<uint64_t>(t) >> 1;
+        blk = philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid, TAG_WL << 24);
+    }
+    for (; i + 2 <= n_trials; i += 2) {
+        // t is even here; blk is block t/2; the next block is computed in two
+        // halves interleaved with this pair of trials
+        PhiloxRun q = philox_start(seed, (static_cast<uint64_t>(t) >> 1) + 1, gid);
+        philox_rounds<5>(q);
+        trial(blk.x, blk.y);
+        philox_rounds<5>(q);
+        trial(blk.z, blk.w);
+        blk = {q.c0, q.c1, q.c2, q.c3};
+    }
+    if (i < n_trials) {  // one trial left, t even: first half of block t/2
+        const uint64_t b = static_cast<uint64_t>(t) >> 1;
+        blk = philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid, TAG_WL << 24);
+        trial(blk.x, blk.y);
+    }
+    tab[cur] = lng_cur;
     S.e[g] = e;
     S.m[g] = m;
     S.t[g] = t;
@@ -328,12 +387,32 @@ __global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int6
     }
 }
 
+// The sweep kernel: walkers [g_begin, g_begin + g_count) in tiles of WG
+// lanes.  With a grid smaller than the tile count each workgroup runs its
+// tiles one after another (persistent form), which bounds the number of
+// walkers in flight and so the set of table lines competing for the L2; the
+// tile-to-workgroup map is the same at every launch, so a walker stays on the
+// same XCD.
+template <typename RowT>
+__global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int64_t g_count,
+                                               int64_t n_trials) {
+    extern __shared__ unsigned char lds_raw[];
+    RowT* lds = reinterpret_cast<RowT*>(lds_raw);
+    const int lane = threadIdx.x;
+    const int WG = blockDim.x;
+    const int64_t n_tiles = (g_count + WG - 1) / WG;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t gi = tile * WG + lane;
+        if (gi < g_count) sweep_walker<RowT>(S, lds, lane, WG, g_begin + gi, n_trials);
+    }
+}
+
 // ------------------------------------------------------------------ flatness
 // One wavefront per walker scans its table 64 bins at a time, starting where
 // the previous scan failed: the walker is flat iff every visited bin (ln g >
-// 0) has flat_den * H * n_seen >= flat_num * sum H, with sum H = trials made
-// in this stage.  The first failing chunk ends the scan; the latch is set only
-// after a full pass.
+// 0) has flat_den * H * n_seen >= flat_num * sum H, with H = (ln g -
+// snapshot) >> (K - s) and sum H = trials made in this stage.  The first
+// failing chunk ends the scan; the latch is set only after a full pass.
 __global__ void __launch_bounds__(256) k_flat(DevState S) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t g = static_cast<int64_t>(blockIdx.x) * 4 + wave;
@@ -342,12 +421,13 @@ __global__ void __launch_bounds__(256) k_flat(DevState S) {
     const int p = d.prob;
     if (S.done[p] || S.flag[g]) return;
     const PDesc P = S.pd[p];
-    const uint64_t s = static_cast<uint64_t>(S.stage[p]);
+    const int sh = P.K - S.stage[p];
     const uint64_t n = S.nseen[g];
     const uint64_t sum = static_cast<uint64_t>(S.t[g] - S.tstage[p]);
     if (n == 0) return;
-    const Bin* tab = S.tables + d.table_off;
-    const int64_t nb = static_cast<int64_t>(d.hi - d.lo + 1) * (P.N + 1);
+    const int64_t* tab = S.lng + d.table_off;
+    const int64_t* snp = S.snap + d.table_off;
+    const int64_t nb = d.nbins;
     const int64_t nch = (nb + 63) / 64;
     int64_t c0 = S.scan[g];
     if (c0 >= nch) c0 = 0;
@@ -358,9 +438,9 @@ __global__ void __launch_bounds__(256) k_flat(DevState S) {
         const int64_t i = c * 64 + lane;
         int fail = 0;
         if (i < nb) {
-            const Bin b = tab[i];
-            if (b.lng != 0) {
-                const uint64_t H = ((b.hs & STAMP_MASK) == s) ? (b.hs >> STAMP_BITS) : 0;
+            const int64_t l = tab[i];
+            if (l != 0) {
+                const uint64_t H = static_cast<uint64_t>(l - snp[i]) >> sh;
                 fail = static_cast<unsigned __int128>(static_cast<uint64_t>(P.flat_den)) * H * n < rhs;
             }
         }
@@ -374,12 +454,13 @@ __global__ void __launch_bounds__(256) k_flat(DevState S) {
 
 // ------------------------------------------------------------------ stage
 // Per problem: when every walker is flat, all move to the next stage together
-// (ln f halves; H restarts from zero through the stage stamp); flatness at
-// the last stage ends the problem.  Otherwise the boundary's exchange round
-// is armed.  Also guards the int64 headroom of ln g.
+// (ln f halves; H restarts from zero through a new snapshot of ln g); flatness
+// at the last stage ends the problem.  Otherwise the boundary's exchange
+// round is armed.  Also guards the int64 headroom of ln g.
 __global__ void k_stage(DevState S) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= S.n_prob) return;
+    S.adv[p] = 0;
     if (S.done[p]) {
         S.xon[p] = 0;
         return;
@@ -405,12 +486,24 @@ __global__ void k_stage(DevState S) {
             return;
         }
         S.stage[p] += 1;
-        S.tstage[p] = S.t[P.walker_off];
+        S.tstage[p] = tnow;
+        S.adv[p] = 1;
         for (int i = 0; i < nw; ++i) S.flag[P.walker_off + i] = 0;
     }
     S.xr[p] = r;
     S.xon[p] = 1;
     S.rnd[p] = r + 1;
+}
+
+// Snapshot of ln g for the walkers of problems that just changed stage: one
+// workgroup per walker, a coalesced copy of its table.
+__global__ void __launch_bounds__(256) k_snapshot(DevState S) {
+    const int64_t g = blockIdx.x;
+    const WDesc d = S.wd[g];
+    if (!S.adv[d.prob]) return;
+    const int64_t* src = S.lng + d.table_off;
+    int64_t* dst = S.snap + d.table_off;
+    for (uint32_t i = threadIdx.x; i < d.nbins; i += blockDim.x) dst[i] = src[i];
 }
 
 // ------------------------------------------------------------------ exchange
@@ -442,7 +535,6 @@ __global__ void __launch_bounds__(64) k_exchange(DevState S) {
             perm[i] = perm[j];
             perm[j] = tmp;
         }
-        const uint64_t stride = static_cast<uint64_t>(P.N) + 1;
         int n = 0;
         for (int a = 0; a < W; ++a) {
             const int A = P.walker_off + w * W + a;
@@ -450,13 +542,10 @@ __global__ void __launch_bounds__(64) k_exchange(DevState S) {
             const WDesc dA = S.wd[A], dB = S.wd[B];
             const int eA = S.e[A], mA = S.m[A], eB = S.e[B], mB = S.m[B];
             if (eA < dB.lo || eA > dB.hi || eB < dA.lo || eB > dA.hi) continue;
-            const Bin* tA = S.tables + dA.table_off;
-            const Bin* tB = S.tables + dB.table_off;
-            const int64_t delta =
-                tA[static_cast<uint64_t>(eA - dA.lo) * stride + mA].lng -
-                tA[static_cast<uint64_t>(eB - dA.lo) * stride + mB].lng +
-                tB[static_cast<uint64_t>(eB - dB.lo) * stride + mB].lng -
-                tB[static_cast<uint64_t>(eA - dB.lo) * stride + mA].lng;
+            const int64_t* tA = S.lng + dA.table_off;
+            const int64_t* tB = S.lng + dB.table_off;
+            const int64_t delta = tA[tile_index(eA - dA.lo, mA, dA.ntm)] - tA[tile_index(eB - dA.lo, mB, dA.ntm)] +
+                                  tB[tile_index(eB - dB.lo, mB, dB.ntm)] - tB[tile_index(eA - dB.lo, mA, dB.ntm)];
             const Words4 b = philox4x32_10(P.seed, r_lo, r_hi, static_cast<uint32_t>(w),
                                            (TAG_XACC << 24) | static_cast<uint32_t>(a));
             if (accept_move(delta, b.x, P.K)) {
@@ -508,9 +597,10 @@ hipError_t launch_entry(const DevState& S, int64_t cap, hipStream_t st) {
 }
 
 hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int64_t n_trials,
-                        int l_max, int wg, hipStream_t st) {
+                        int l_max, int wg, int max_grid, hipStream_t st) {
     if (g_count <= 0 || n_trials <= 0) return hipSuccess;
-    const int grid = blocks_for(g_count, wg);
+    int grid = blocks_for(g_count, wg);
+    if (max_grid > 0 && grid > max_grid) grid = max_grid;
     if (l_max <= 32) {
         const size_t lds = static_cast<size_t>(l_max) * wg * sizeof(uint32_t);
         hipLaunchKernelGGL(k_sweep<uint32_t>, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials);
@@ -536,6 +626,12 @@ hipError_t launch_flat(const DevState& S, hipStream_t st) {
 
 hipError_t launch_stage(const DevState& S, hipStream_t st) {
     hipLaunchKernelGGL(k_stage, dim3(blocks_for(S.n_prob, 64)), dim3(64), 0, st, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_snapshot(const DevState& S, hipStream_t st) {
+    if (S.n_walk == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_snapshot, dim3(static_cast<unsigned>(S.n_walk)), dim3(256), 0, st, S);
     return hipGetLastError();
 }
 

@@ -59,7 +59,10 @@ def test_plan_validation_and_windows_on_host():
             assert (lo.value, hi.value) == window(256, 8, 3, 4, w)
         sizes = (C.c_size_t * 3)()
         assert L.rewl_plan_buffer_sizes(h, sizes) == 0
-        bins = sum((window(256, 8, 3, 4, w)[1] - window(256, 8, 3, 4, w)[0] + 1) * 257 * 4 for w in range(8))
+        # ln g and snapshot tables, 8 bytes per bin, in 4x4 tiles of (e, m), 4 walkers per window
+        tiles = sum(-(-(window(256, 8, 3, 4, w)[1] - window(256, 8, 3, 4, w)[0] + 1) // 4) * -(-257 // 4)
+                    for w in range(8))
+        bins = tiles * 16 * 4
         assert sizes[0] >= bins * 16 and sizes[0] < bins * 16 + 256
         # calls needing device buffers fail cleanly before bind
         assert L.rewl_init(h) == R.REWL_ESTATE

@@ -181,3 +181,19 @@ def test_init_all_up_entry_walks():
     plan.run(4)
     orc.run(4)
     compare(plan, 0, orc)
+
+
+def test_persistent_grid_loops_over_tiles():
+    R = _R()
+    # 600 problems x 32 walkers = 19,200 walkers = 300 tiles of 64 lanes, on a
+    # grid of 256 workgroups (1 wavefront per CU): workgroups run several tiles
+    probs = [R.Problem(L=4, n_windows=2, overlap=(1, 2), walkers_per_window=16, k_final=8, interval=300, seed=s)
+             for s in range(600)]
+    _say("case: persistent grid, 300 tiles on 256 workgroups")
+    plan = R.Plan(probs, R.Tuning(walkers_per_wg=64, grid_waves_per_cu=1, graph_intervals=2))
+    plan.init()
+    plan.run(6)
+    for i in (0, 1, 299, 598, 599):
+        o = _oracle_of(probs[i])
+        o.run(6)
+        compare(plan, i, o)

@@ -1,0 +1,141 @@
+"""Reweighting ln Z(beta, h) on the GPU (C ABI) against the float64 oracle.
+
+Tolerances come from the arithmetic: every term is one exp (<= 2 ulp) of an
+exactly formed float64 exponent, and sums of positive terms in a different
+order differ by a few ulp per term at most, so ln Z agrees to ~1e-13 absolute
+(1e-10 allowed); first moments to ~1e-12 relative and central second moments
+(computed about the means, no cancellation of raw moments) to ~1e-10 relative
+(1e-8 allowed, with an absolute floor scaled by N for moments that vanish).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import exact
+from oracle import lnz as Z
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1508_02748_amd as R
+    R.lib()
+    return torch, R
+
+
+def _synthetic(L):
+    N = L * L
+    lge = exact.exact_lngE(L)
+    return lge[:, None] + exact.binomial_lng(N)[None, :] - N * math.log(2.0), N
+
+
+def _grid(nb, nh):
+    b = np.linspace(0.1, 1.0, nb)
+    h = np.linspace(-0.5, 0.5, nh)
+    B, Hh = np.meshgrid(b, h, indexing="ij")
+    return B.ravel(), Hh.ravel()
+
+
+def test_forward_and_moments_4x4_and_synthetic():
+    torch, R = _torch()
+    G4 = exact.enumerate_joint(4)
+    with np.errstate(divide="ignore"):
+        lng4 = np.where(G4 > 0, np.log(np.maximum(G4, 1)), -np.inf)
+    for lng, N in ((lng4, 16), _synthetic(8), _synthetic(16)):
+        b, h = _grid(9, 7)
+        dl = torch.tensor(lng, device="cuda")
+        db, dh = torch.tensor(b, device="cuda"), torch.tensor(h, device="cuda")
+        z = R.lnz_forward(dl, db, dh, N)
+        ref = Z.moments(lng, b, h)
+        assert np.max(np.abs(z.cpu().numpy() - ref["lnz"])) < 1e-10
+        mom = R.lnz_moments(dl, db, dh, z, N).cpu().numpy()
+        for col, key, scale in ((0, "M", N), (1, None, None), (2, "varU", None), (3, "varM", None),
+                                (4, "covUM", None)):
+            if key is None:
+                want = -ref["E"] + h * ref["M"]
+            else:
+                want = ref[key]
+            got = mom[:, col]
+            tol = 1e-8 * np.maximum(np.abs(want), 1.0) + 1e-9 * N
+            assert np.all(np.abs(got - want) <= tol), (N, col, np.max(np.abs(got - want)))
+
+
+def test_sub_table_geometry_offsets():
+    torch, R = _torch()
+    lng, N = _synthetic(8)
+    # a window of rows / columns: the missing bins count as unvisited
+    e0, e1, m0, m1 = 5, 50, 3, 60
+    sub = np.full_like(lng, -np.inf)
+    sub[e0:e1, m0:m1] = lng[e0:e1, m0:m1]
+    b, h = _grid(5, 5)
+    db, dh = torch.tensor(b, device="cuda"), torch.tensor(h, device="cuda")
+    dl = torch.tensor(np.ascontiguousarray(lng[e0:e1, m0:m1]), device="cuda")
+    z = R.lnz_forward(dl, db, dh, N, e0=e0, m0=m0).cpu().numpy()
+    assert np.max(np.abs(z - Z.lnz(sub, b, h))) < 1e-10
+
+
+def test_autograd_matches_oracle_and_finite_differences():
+    torch, R = _torch()
+    LnZ = R.LnZ()
+    lng, N = _synthetic(6)
+    lng = lng + np.random.default_rng(1).normal(0, 0.2, lng.shape)
+    b, h = _grid(4, 3)
+    dl = torch.tensor(lng, device="cuda", requires_grad=True)
+    db = torch.tensor(b, device="cuda", requires_grad=True)
+    dh = torch.tensor(h, device="cuda", requires_grad=True)
+    go = torch.linspace(0.5, 1.5, b.size, dtype=torch.float64, device="cuda")
+    z = LnZ.apply(dl, db, dh, N)
+    gl, gb, gh = torch.autograd.grad(z, (dl, db, dh), go)
+    rb, rh, rl = Z.grads(lng, b, h, go.cpu().numpy())
+    assert np.allclose(gb.cpu().numpy(), rb, rtol=1e-9, atol=1e-9)
+    assert np.allclose(gh.cpu().numpy(), rh, rtol=1e-9, atol=1e-9)
+    assert np.allclose(gl.cpu().numpy(), rl, rtol=1e-9, atol=1e-12)
+    # finite differences, first and second order, through torch's own checkers
+    f = lambda bb, hh: LnZ.apply(dl.detach(), bb, hh, N)
+    assert torch.autograd.gradcheck(f, (db, dh), eps=1e-6, atol=1e-6, rtol=1e-5)
+    assert torch.autograd.gradgradcheck(f, (db, dh), eps=1e-5, atol=1e-5, rtol=1e-4)
+
+
+def test_specific_heat_and_susceptibility_from_second_derivatives():
+    torch, R = _torch()
+    LnZ = R.LnZ()
+    lng, N = _synthetic(8)
+    b, h = _grid(6, 5)
+    dl = torch.tensor(lng, device="cuda")
+    db = torch.tensor(b, device="cuda", requires_grad=True)
+    dh = torch.tensor(h, device="cuda", requires_grad=True)
+    z = LnZ.apply(dl, db, dh, N)
+    gb, gh = torch.autograd.grad(z.sum(), (db, dh), create_graph=True)
+    gbb, = torch.autograd.grad(gb.sum(), (db,), retain_graph=True)
+    ghh, = torch.autograd.grad(gh.sum(), (dh,))
+    ref = Z.moments(lng, b, h)
+    C = (db * db * gbb / N).detach().cpu().numpy()             # beta^2 Var(E - hM) / N
+    chi = (ghh / (db * N)).detach().cpu().numpy()              # beta Var(M) / N
+    assert np.allclose(C, b * b * ref["varU"] / N, rtol=1e-8)
+    assert np.allclose(chi, b * ref["varM"] / N, rtol=1e-8)
+    # closed form of the synthetic table: Var(M) = N / cosh^2(beta h)
+    assert np.allclose(ref["varM"], N / np.cosh(b * h) ** 2, rtol=1e-8)
+
+
+def test_full_size_grid_on_32x32_sampled():
+    torch, R = _torch()
+    lng, N = _synthetic(32)                         # 1025 x 1025 bins
+    b, h = _grid(1024, 256)                         # 262,144 grid points
+    dl = torch.tensor(lng, device="cuda")
+    db, dh = torch.tensor(b, device="cuda"), torch.tensor(h, device="cuda")
+    z = R.lnz_forward(dl, db, dh, N)
+    mom = R.lnz_moments(dl, db, dh, z, N)
+    z, mom = z.cpu().numpy(), mom.cpu().numpy()
+    idx = np.r_[0, 1, 255, 256, 1000, 77777, 131072, 200001, 262142, 262143]
+    ref = Z.moments(lng, b[idx], h[idx])
+    assert np.max(np.abs(z[idx] - ref["lnz"])) < 1e-9
+    assert np.allclose(mom[idx, 0], ref["M"], rtol=1e-8, atol=1e-8 * N)
+    assert np.allclose(mom[idx, 3], ref["varM"], rtol=1e-8)
+    # property at every grid point: the synthetic table factorises
+    lz0 = Z.lnz(lng, b[::256], 0.0 * b[::256])
+    expect = np.repeat(lz0, 256) + N * np.log(np.cosh(b * h))
+    assert np.max(np.abs(z - expect)) < 1e-9 * np.max(np.abs(expect))

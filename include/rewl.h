@@ -23,7 +23,8 @@
  *     device pointers (any allocator; the Python binding uses PyTorch) and a
  *     hipStream_t.  The library never frees them; they must outlive the plan.
  *   - All device work is enqueued on the bound stream.  Only rewl_init,
- *     rewl_query, rewl_read_walker and rewl_merge_lng synchronise it.
+ *     rewl_query, rewl_read_walker, rewl_merge_lng and rewl_sweep_times
+ *     synchronise it.
  *   - Arguments are validated before any device work (REWL_EINVAL).  A HIP
  *     error surfaces as REWL_EDEVICE; after it the plan answers REWL_ESTATE
  *     to every call but rewl_plan_destroy.
@@ -146,6 +147,25 @@ rewl_status rewl_query(rewl_plan* plan, int32_t* stage_out, int32_t* done_out,
 rewl_status rewl_read_walker(rewl_plan* plan, int32_t prob, int32_t w, int32_t a,
                              int64_t* lng, uint64_t* H, size_t cap_bins, int8_t* spins,
                              int32_t* e, int32_t* m, int64_t* t);
+
+/* Joining the fragments of problem prob into one joint DOS (Sec. 2):
+ * walkers of a window are aligned on their mean over the bins all of them
+ * visited and averaged; Eq. (3) gives each window's ln g(E) = log sum_M g;
+ * the matching point E_mat of neighbouring windows minimises the difference
+ * of beta(E) = d ln g / dE (central differences (ln g(E+4) - ln g(E-4))/8)
+ * over their overlap, at or above the previous matching point, ties to the
+ * lowest E; the upper window is shifted by one constant to agree there and
+ * Eq. (4) takes the lower window below E_mat and the upper from E_mat on.
+ * norm 0: ln g(E = -2N) = ln 2 (the two ground states); 1: sum g = 2^N.
+ * Device outputs: lng_out (N+1) x (N+1) float64 by (e, m), -inf where no
+ * walker visited; lnge_out (N+1) the marginal ln g(E) of that table;
+ * e_mat_out (nullable) n_windows - 1 matching energy bins.  `workspace` is
+ * device memory of rewl_merge_workspace_size bytes.  Synchronises;
+ * REWL_ESTATE when a window's walkers share no visited bin or two windows
+ * have no usable matching point. */
+rewl_status rewl_merge_workspace_size(const rewl_plan* plan, int32_t prob, size_t* bytes);
+rewl_status rewl_merge_lng(rewl_plan* plan, int32_t prob, int32_t norm, void* workspace, size_t workspace_bytes,
+                           double* lng_out, double* lnge_out, int32_t* e_mat_out);
 
 /* Reweighting of a joint DOS (float64 ln g over bins (e, m), -inf = not
  * visited) into ln Z(beta, h) = log sum exp(ln g - beta E + beta h M) at G

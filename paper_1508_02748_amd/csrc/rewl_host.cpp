@@ -729,3 +729,81 @@ extern "C" rewl_status rewl_sweep_times(rewl_plan* P, float* ms, int32_t cap, in
     *count = P->ev_used;
     return REWL_OK;
 }
+
+namespace {
+
+struct MergeLayout {
+    size_t bytes = 0;
+    MergeGeo G{};
+    int max_nE = 0;
+};
+
+rewl_status merge_layout(const rewl_plan* P, int32_t prob, char* base, MergeLayout& out) {
+    if (prob < 0 || prob >= static_cast<int32_t>(P->pd.size())) return fail(REWL_EINVAL, "problem out of range");
+    const PDesc& q = P->pd[prob];
+    if (q.nwin > MERGE_MAX_WINDOWS) return fail(REWL_EINVAL, "merge supports at most 256 windows");
+    const int64_t nM = q.N + 1;
+    int64_t o = 0;
+    MergeGeo G{};
+    G.prob = prob;
+    G.off_shift = o;
+    o += static_cast<int64_t>(q.nwin) * q.W;
+    G.off_marg = o;
+    o += static_cast<int64_t>(q.nwin) * nM;
+    G.off_mg = o;
+    o += nM;
+    G.off_pshift = o;
+    o += q.nwin;
+    G.off_cst = o;
+    o += 1;
+    int max_nE = 0;
+    for (int w = 0; w < q.nwin; ++w) {
+        const int nE = P->hi[prob][w] - P->lo[prob][w] + 1;
+        max_nE = std::max(max_nE, nE);
+        G.off_avg[w] = o;
+        o += static_cast<int64_t>(nE) * nM;
+    }
+    const size_t dbl_bytes = align_up(static_cast<size_t>(o) * sizeof(double), 256);
+    // integer region (256-byte aligned): 4 flags (16 bytes, cleared with one
+    // 16-byte store), then the matching points
+    out.bytes = dbl_bytes + align_up(16 + static_cast<size_t>(q.nwin) * sizeof(int32_t), 256);
+    G.ws = reinterpret_cast<double*>(base);
+    G.flags = reinterpret_cast<int32_t*>(base + dbl_bytes);
+    G.emat = G.flags + 4;
+    out.G = G;
+    out.max_nE = max_nE;
+    return REWL_OK;
+}
+
+}  // namespace
+
+extern "C" rewl_status rewl_merge_workspace_size(const rewl_plan* P, int32_t prob, size_t* bytes) {
+    if (!P || !bytes) return fail(REWL_EINVAL, "null argument");
+    MergeLayout ml;
+    rewl_status s = merge_layout(P, prob, nullptr, ml);
+    if (s != REWL_OK) return s;
+    *bytes = ml.bytes;
+    return REWL_OK;
+}
+
+extern "C" rewl_status rewl_merge_lng(rewl_plan* P, int32_t prob, int32_t norm, void* workspace, size_t ws_bytes,
+                                      double* lng_out, double* lnge_out, int32_t* e_mat_out) {
+    rewl_status s = usable(P);
+    if (s != REWL_OK) return s;
+    if (!P->initialised) return fail(REWL_ESTATE, "rewl_init has not run");
+    if (norm != 0 && norm != 1) return fail(REWL_EINVAL, "norm must be 0 (ground state) or 1 (sum)");
+    if (!workspace || !lng_out || !lnge_out) return fail(REWL_EINVAL, "null device pointer");
+    MergeLayout ml;
+    if ((s = merge_layout(P, prob, static_cast<char*>(workspace), ml)) != REWL_OK) return s;
+    if (ws_bytes < ml.bytes) return fail(REWL_EINVAL, "workspace too small");
+    const PDesc& q = P->pd[prob];
+    HIPCHK(P, launch_zero(ml.G.flags, 16, P->stream), "merge flag clear");
+    HIPCHK(P, launch_merge(P->S, ml.G, q.N, q.nwin, ml.max_nE, norm, lng_out, lnge_out, e_mat_out, P->stream),
+           "merge launch");
+    int32_t flags[4];
+    HIPCHK(P, hipMemcpyAsync(flags, ml.G.flags, 16, hipMemcpyDeviceToHost, P->stream), "merge flag read");
+    HIPCHK(P, hipStreamSynchronize(P->stream), "merge sync");
+    if (flags[0] == 1) return fail(REWL_ESTATE, "the walkers of a window share no visited bin");
+    if (flags[0] == 2) return fail(REWL_ESTATE, "no matching point in the overlap of two windows");
+    return REWL_OK;
+}

@@ -85,6 +85,21 @@ struct DevState {
 
 enum : int32_t { ERR_OVERFLOW = 1 };
 
+// Workspace of the merge of one problem (offsets in doubles from ws).
+constexpr int MERGE_MAX_WINDOWS = 256;
+struct MergeGeo {
+    int32_t prob;
+    double* ws;
+    int64_t off_shift;   // n_windows * W alignment constants
+    int64_t off_marg;    // n_windows * (N + 1) window marginals (Eq. 3)
+    int64_t off_mg;      // N + 1: marginal of the pieces joined so far
+    int64_t off_pshift;  // n_windows additive constants of the pieces
+    int64_t off_cst;     // normalisation constant
+    int64_t off_avg[MERGE_MAX_WINDOWS];  // window-averaged tables, (hi-lo+1) x (N+1)
+    int32_t* emat;       // n_windows matching points (emat[0] = 0)
+    int32_t* flags;      // [0] != 0: no common bin (1) or no matching point (2)
+};
+
 // Launchers (rewl_kernels.hip).  All enqueue on `st` and return the launch status.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_init(const DevState& S, hipStream_t st);
@@ -96,6 +111,9 @@ hipError_t launch_flat(const DevState& S, hipStream_t st);
 hipError_t launch_stage(const DevState& S, hipStream_t st);
 hipError_t launch_snapshot(const DevState& S, hipStream_t st);
 hipError_t launch_exchange(const DevState& S, hipStream_t st);
+
+hipError_t launch_merge(const DevState& S, const MergeGeo& G, int N, int nwin, int max_nE, int norm,
+                        double* lng_out, double* lnge_out, int32_t* e_mat_out, hipStream_t st);
 
 // Reweighting.
 hipError_t launch_lnz_forward(const double* lng, int N, int e0, int nE, int m0, int nM,

@@ -1,0 +1,77 @@
+"""Device-side merge (Eq. 3, E_mat, Eq. 4, normalisation) against oracle/merge.py.
+
+Both sides start from bit-identical ln g tables (the sampling is bit-exact), so
+differences come only from float64 rounding order: the alignment means (an
+exact integer sum on the device, numpy's pairwise sum in the oracle) and the
+log-sum-exp reductions, each a few ulp of values below ~1e4, so ln g agrees to
+~1e-11 absolute (1e-9 allowed).  Matching points are compared exactly.
+"""
+import numpy as np
+import pytest
+
+from oracle import exact
+from oracle import merge as MG
+from oracle.rewl import OracleREWL
+
+pytestmark = pytest.mark.gpu
+
+
+def _R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1508_02748_amd as R
+    R.lib()
+    return R
+
+
+def _pair(R, p, n_intervals):
+    plan = R.Plan([p])
+    plan.init()
+    plan.run(n_intervals)
+    o = OracleREWL(p.L, p.n_windows, p.overlap, p.walkers_per_window, p.k_final, p.flat, p.interval,
+                   p.seed, p.init)
+    o.init()
+    o.run(n_intervals)
+    return plan, o
+
+
+def _check(plan, o, norm):
+    j, g, em = plan.merge(0, norm)
+    j, g = j.cpu().numpy(), g.cpu().numpy()
+    rj, rg, rem = MG.merge_oracle_run(o, norm)
+    assert em == rem, (em, rem)
+    fin = np.isfinite(rj)
+    assert (np.isfinite(j) == fin).all()
+    assert np.max(np.abs(j[fin] - rj[fin])) < 1e-9
+    gf = np.isfinite(rg)
+    assert (np.isfinite(g) == gf).all()
+    assert np.max(np.abs(g[gf] - rg[gf])) < 1e-9
+    return j, g
+
+
+@pytest.mark.parametrize("norm", ["ground", "sum"])
+def test_merge_8x8_rewl_matches_oracle(norm):
+    R = _R()
+    p = R.Problem(L=8, n_windows=3, walkers_per_window=2, k_final=8, interval=1000, seed=2)
+    plan, o = _pair(R, p, 300)
+    _check(plan, o, norm)
+
+
+def test_merge_16x16_prefix_matches_oracle():
+    R = _R()
+    p = R.Problem(L=16, n_windows=8, walkers_per_window=4, k_final=20, interval=10_000, seed=0)
+    plan, o = _pair(R, p, 120)
+    _check(plan, o, "sum")
+
+
+def test_merge_single_window_4x4_full_run():
+    R = _R()
+    p = R.Problem(L=4, n_windows=1, walkers_per_window=1, k_final=16, interval=10_000, seed=0)
+    plan, o = _pair(R, p, 400)
+    assert o.info()["done"]
+    j, g = _check(plan, o, "sum")
+    G = exact.enumerate_joint(4)
+    mask = G > 0
+    assert (np.isfinite(j) == mask).all()
+    assert np.max(np.abs(j[mask] - np.log(G[mask]))) < 0.2

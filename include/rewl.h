@@ -188,6 +188,19 @@ rewl_status rewl_lnz_backward(const double* lng, int32_t N, int32_t e0, int32_t 
                               double* grad_beta, double* grad_h, double* grad_lng,
                               double* mom, int32_t order, void* hip_stream);
 
+/* Replace the tuning of a plan (same form); results do not change. */
+rewl_status rewl_set_tuning(rewl_plan* plan, const rewl_tuning* tuning);
+
+/* Checkpoint / resume at an interval boundary.  The Philox counters are part
+ * of the state, so a resumed run continues bit for bit.  rewl_save writes
+ * the problems and all three device buffers into a host blob of
+ * rewl_save_size bytes (synchronises); rewl_load restores them into a plan
+ * created from the same problems and bound to its own buffers (synchronises);
+ * REWL_EINVAL for a truncated blob or one saved from other problems. */
+rewl_status rewl_save_size(const rewl_plan* plan, size_t* bytes);
+rewl_status rewl_save(rewl_plan* plan, void* blob, size_t cap, size_t* used);
+rewl_status rewl_load(rewl_plan* plan, const void* blob, size_t size);
+
 /* Profiling of the batched form: while on, rewl_run enqueues its intervals
  * one launch at a time (not from the graph) with a HIP event pair around
  * every sweep kernel; rewl_sweep_times then gives those kernels' durations

@@ -273,6 +273,8 @@ static int dist_to(const or_rewl *P, int w, int e) {
 OR_EXPORT int or_init(or_rewl *P, int64_t entry_cap) {
     int N = P->N;
     int bad = 0;
+    /* walkers are independent until the first boundary */
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
     for (int g = 0; g < P->nwalk; ++g) {
         int8_t *s = P->spin + (size_t)g * N;
         if (P->init == 1) {
@@ -299,7 +301,7 @@ OR_EXPORT int or_init(or_rewl *P, int64_t entry_cap) {
         int w = win_of(P, g);
         int d = dist_to(P, w, P->e[g]);
         while (d > 0) {
-            if (P->te[g] >= entry_cap) { bad = 1; break; }
+            if (P->te[g] >= entry_cap) { bad |= 1; break; }
             uint32_t sw, uw;
             draw_pair(P->seed, (uint64_t)P->te[g], (uint32_t)g, TAG_ENTRY, &sw, &uw);
             int site = site_of(sw, N);

@@ -78,6 +78,10 @@ def lib():
             "rewl_sweep_times": ([P, P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
             "rewl_set_profile": ([P, C.c_int32], C.c_int),
             "rewl_merge_workspace_size": ([P, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
+            "rewl_set_tuning": ([P, C.POINTER(_Tuning)], C.c_int),
+            "rewl_save_size": ([P, C.POINTER(C.c_size_t)], C.c_int),
+            "rewl_save": ([P, P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
+            "rewl_load": ([P, P, C.c_size_t], C.c_int),
             "rewl_merge_lng": ([P, C.c_int32, C.c_int32, P, C.c_size_t, P, P, P], C.c_int),
             "rewl_last_error": ([], C.c_char_p),
         }
@@ -139,6 +143,7 @@ class Plan:
         self.problems = list(problems)
         arr = (_Problem * len(self.problems))(*[p._c() for p in self.problems])
         h = C.c_void_p()
+        self.tuning = tuning if tuning is not None else Tuning()
         tn = None if tuning is None else C.byref(tuning._c())
         _check(lib().rewl_plan_create(arr, len(self.problems), tn, C.byref(h)))
         self._h = h
@@ -188,6 +193,23 @@ class Plan:
         tr = np.zeros(n, np.int64)
         _check(lib().rewl_query(self._h, st.ctypes.data, dn.ctypes.data, tr.ctypes.data))
         return {"stage": st, "done": dn.astype(bool), "trials": tr}
+
+    def set_tuning(self, tuning):
+        self.tuning = tuning
+        _check(lib().rewl_set_tuning(self._h, C.byref(tuning._c())))
+
+    def save(self):
+        """Checkpoint: bytes holding the problems and the whole device state."""
+        n = C.c_size_t()
+        _check(lib().rewl_save_size(self._h, C.byref(n)))
+        buf = np.empty(n.value, np.uint8)
+        used = C.c_size_t()
+        _check(lib().rewl_save(self._h, buf.ctypes.data, n.value, C.byref(used)))
+        return buf[:used.value].tobytes()
+
+    def load(self, blob):
+        arr = np.frombuffer(blob, np.uint8)
+        _check(lib().rewl_load(self._h, arr.ctypes.data, arr.size))
 
     def set_profile(self, on):
         _check(lib().rewl_set_profile(self._h, 1 if on else 0))

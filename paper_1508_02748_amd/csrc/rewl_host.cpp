@@ -114,6 +114,19 @@ rewl_status validate(const rewl_problem& q, int idx) {
     return REWL_OK;
 }
 
+rewl_status validate_tuning(const rewl_tuning& tn) {
+    if (tn.form != REWL_FORM_BATCHED && tn.form != REWL_FORM_PLAIN) return fail(REWL_EINVAL, "unknown form");
+    if (tn.walkers_per_wg != 0 && tn.walkers_per_wg != 64 && tn.walkers_per_wg != 128 && tn.walkers_per_wg != 256)
+        return fail(REWL_EINVAL, "walkers_per_wg must be 0, 64, 128 or 256");
+    if (tn.graph_intervals < 0 || tn.graph_intervals > 4096) return fail(REWL_EINVAL, "graph_intervals 0..4096");
+    if (tn.grid_waves_per_cu < 0 || tn.grid_waves_per_cu > 64) return fail(REWL_EINVAL, "grid_waves_per_cu 0..64");
+    if (tn.profile != 0 && tn.profile != 1) return fail(REWL_EINVAL, "profile must be 0 or 1");
+    if (tn.profile && tn.form != REWL_FORM_BATCHED) return fail(REWL_EINVAL, "profiling times the batched form");
+    for (int r : tn.reserved)
+        if (r != 0) return fail(REWL_EINVAL, "tuning.reserved must be 0");
+    return REWL_OK;
+}
+
 DevState make_state(rewl_plan* P) {
     DevState S{};
     char* st = static_cast<char*>(P->buf[REWL_BUF_STATE]);
@@ -333,16 +346,8 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
     rewl_tuning tn{};
     if (tuning) {
         tn = *tuning;
-        if (tn.form != REWL_FORM_BATCHED && tn.form != REWL_FORM_PLAIN) return fail(REWL_EINVAL, "unknown form");
-        if (tn.walkers_per_wg != 0 && tn.walkers_per_wg != 64 && tn.walkers_per_wg != 128 &&
-            tn.walkers_per_wg != 256)
-            return fail(REWL_EINVAL, "walkers_per_wg must be 0, 64, 128 or 256");
-        if (tn.graph_intervals < 0 || tn.graph_intervals > 4096) return fail(REWL_EINVAL, "graph_intervals 0..4096");
-        if (tn.grid_waves_per_cu < 0) return fail(REWL_EINVAL, "grid_waves_per_cu must be >= 0");
-        if (tn.profile != 0 && tn.profile != 1) return fail(REWL_EINVAL, "profile must be 0 or 1");
-        if (tn.profile && tn.form != REWL_FORM_BATCHED) return fail(REWL_EINVAL, "profiling times the batched form");
-        for (int r : tn.reserved)
-            if (r != 0) return fail(REWL_EINVAL, "tuning.reserved must be 0");
+        rewl_status ts = validate_tuning(tn);
+        if (ts != REWL_OK) return ts;
     }
     const int64_t X = problems[0].interval;
     for (int i = 1; i < n_problems; ++i)
@@ -805,5 +810,89 @@ extern "C" rewl_status rewl_merge_lng(rewl_plan* P, int32_t prob, int32_t norm, 
     HIPCHK(P, hipStreamSynchronize(P->stream), "merge sync");
     if (flags[0] == 1) return fail(REWL_ESTATE, "the walkers of a window share no visited bin");
     if (flags[0] == 2) return fail(REWL_ESTATE, "no matching point in the overlap of two windows");
+    return REWL_OK;
+}
+
+extern "C" rewl_status rewl_set_tuning(rewl_plan* P, const rewl_tuning* tuning) {
+    if (!P || !tuning) return fail(REWL_EINVAL, "null argument");
+    if (P->broken) return fail(REWL_ESTATE, "plan is in an error state");
+    rewl_status s = validate_tuning(*tuning);
+    if (s != REWL_OK) return s;
+    if (tuning->form != P->tune.form) return fail(REWL_EINVAL, "the form of a plan cannot change");
+    P->tune = *tuning;
+    P->profile = tuning->profile != 0;
+    if (P->graph) {
+        (void)hipGraphExecDestroy(P->graph);
+        P->graph = nullptr;
+        P->graph_g = 0;
+    }
+    return REWL_OK;
+}
+
+namespace {
+constexpr uint64_t SAVE_MAGIC = 0x3130574C57455232ull;  // "2REWLW01"
+struct SaveHeader {
+    uint64_t magic;
+    uint64_t n_problems;
+    uint64_t sizes[REWL_NBUF];
+};
+}  // namespace
+
+extern "C" rewl_status rewl_save_size(const rewl_plan* P, size_t* bytes) {
+    if (!P || !bytes) return fail(REWL_EINVAL, "null argument");
+    size_t n = sizeof(SaveHeader) + P->probs.size() * sizeof(rewl_problem);
+    for (int i = 0; i < REWL_NBUF; ++i) n += P->sizes[i];
+    *bytes = n;
+    return REWL_OK;
+}
+
+extern "C" rewl_status rewl_save(rewl_plan* P, void* blob, size_t cap, size_t* used) {
+    rewl_status s = usable(P);
+    if (s != REWL_OK) return s;
+    if (!P->initialised) return fail(REWL_ESTATE, "rewl_init has not run");
+    size_t need = 0;
+    rewl_save_size(P, &need);
+    if (!blob || cap < need) return fail(REWL_EINVAL, "blob too small (see rewl_save_size)");
+    char* out = static_cast<char*>(blob);
+    SaveHeader h{SAVE_MAGIC, P->probs.size(), {P->sizes[0], P->sizes[1], P->sizes[2]}};
+    std::memcpy(out, &h, sizeof h);
+    size_t o = sizeof h;
+    std::memcpy(out + o, P->probs.data(), P->probs.size() * sizeof(rewl_problem));
+    o += P->probs.size() * sizeof(rewl_problem);
+    for (int i = 0; i < REWL_NBUF; ++i) {
+        HIPCHK(P, hipMemcpyAsync(out + o, P->buf[i], P->sizes[i], hipMemcpyDeviceToHost, P->stream), "save copy");
+        o += P->sizes[i];
+    }
+    HIPCHK(P, hipStreamSynchronize(P->stream), "save sync");
+    if (used) *used = o;
+    return REWL_OK;
+}
+
+extern "C" rewl_status rewl_load(rewl_plan* P, const void* blob, size_t size) {
+    rewl_status s = usable(P);
+    if (s != REWL_OK) return s;
+    if (!blob || size < sizeof(SaveHeader)) return fail(REWL_EINVAL, "blob truncated");
+    const char* in = static_cast<const char*>(blob);
+    SaveHeader h;
+    std::memcpy(&h, in, sizeof h);
+    if (h.magic != SAVE_MAGIC) return fail(REWL_EINVAL, "not a saved plan (magic)");
+    if (h.n_problems != P->probs.size()) return fail(REWL_EINVAL, "saved plan has other problems");
+    size_t need = 0;
+    rewl_save_size(P, &need);
+    if (size < need) return fail(REWL_EINVAL, "blob truncated");
+    for (int i = 0; i < REWL_NBUF; ++i)
+        if (h.sizes[i] != P->sizes[i]) return fail(REWL_EINVAL, "saved plan has other buffer sizes");
+    if (std::memcmp(in + sizeof h, P->probs.data(), P->probs.size() * sizeof(rewl_problem)) != 0)
+        return fail(REWL_EINVAL, "saved plan has other problems");
+    size_t o = sizeof h + P->probs.size() * sizeof(rewl_problem);
+    for (int i = 0; i < REWL_NBUF; ++i) {
+        HIPCHK(P, hipMemcpyAsync(P->buf[i], in + o, P->sizes[i], hipMemcpyHostToDevice, P->stream), "load copy");
+        o += P->sizes[i];
+    }
+    HIPCHK(P, hipStreamSynchronize(P->stream), "load sync");
+    P->initialised = true;
+    if (P->tune.form == REWL_FORM_BATCHED) {
+        if ((s = ensure_graph(P, graph_len(P))) != REWL_OK) return s;
+    }
     return REWL_OK;
 }

@@ -1,0 +1,68 @@
+"""Runtime features through the C ABI: autotuner, tuning changes, checkpoint /
+resume.  None may change results: every case ends bit-identical to the oracle."""
+import pytest
+
+from tests.test_gpu_parity import _R, _oracle_of, _say, compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _probs(R, n, **kw):
+    base = dict(L=8, n_windows=3, walkers_per_window=4, k_final=10, interval=800)
+    base.update(kw)
+    return [R.Problem(seed=s, **base) for s in range(n)]
+
+
+def test_autotune_restores_state_and_keeps_results():
+    R = _R()
+    from paper_1508_02748_amd.tune import autotune
+    probs = _probs(R, 300)
+    _say("case: autotune on 300 x 12 walkers")
+    plan = R.Plan(probs, R.Tuning(graph_intervals=2))
+    plan.init()
+    plan.run(3)
+    best = autotune(plan, intervals=1, candidates=[(64, 0), (128, 2), (256, 4), (64, 8)], use_cache=False)
+    assert best.walkers_per_wg in (64, 128, 256)
+    plan.run(3)
+    for i in (0, 150, 299):
+        o = _oracle_of(probs[i])
+        o.run(6)
+        compare(plan, i, o)
+
+
+def test_set_tuning_midway_keeps_results():
+    R = _R()
+    probs = _probs(R, 40)
+    plan = R.Plan(probs, R.Tuning(graph_intervals=3))
+    plan.init()
+    plan.run(4)
+    plan.set_tuning(R.Tuning(walkers_per_wg=256, graph_intervals=1, grid_waves_per_cu=1))
+    plan.run(4)
+    o = _oracle_of(probs[7])
+    o.run(8)
+    compare(plan, 7, o)
+
+
+def test_checkpoint_resume_is_bit_exact():
+    R = _R()
+    probs = _probs(R, 5, k_final=6, interval=500)
+    _say("case: save after 6 intervals, resume in a new plan")
+    a = R.Plan(probs)
+    a.init()
+    a.run(6)
+    blob = a.save()
+    a.run(6)
+    b = R.Plan(probs)
+    b.load(blob)
+    b.run(6)
+    for i in range(5):
+        o = _oracle_of(probs[i])
+        o.run(12)
+        compare(a, i, o)
+        compare(b, i, o)
+    c = R.Plan(probs)
+    with pytest.raises(R.RewlError):
+        c.load(blob[: len(blob) // 2])
+    other = R.Plan(_probs(R, 5, k_final=7, interval=500))
+    with pytest.raises(R.RewlError):
+        other.load(blob)

@@ -27,8 +27,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "spin-flip attempts/sec on 1 MI355X (batched vs plain) at equal final ln f"
-# One 16x16 REWL problem: the configuration the throughput is quoted on.
+# One REWL problem of each measured configuration; the 16x16 problem is the
+# one the throughput is quoted on.
 C2 = dict(L=16, n_windows=8, overlap=(3, 4), walkers_per_window=4, k_final=20, flat=(4, 5), interval=10_000)
+C3 = dict(L=32, n_windows=16, overlap=(3, 4), walkers_per_window=8, k_final=24, flat=(4, 5), interval=10_000)
+C4 = dict(L=64, n_windows=64, overlap=(3, 4), walkers_per_window=4, k_final=20, flat=(4, 5), interval=100_000)
+WORKLOADS = {
+    "c2": (C2, 4096, "16x16 periodic Ising 2D-REWL (8 windows x 4 walkers, overlap 3/4, ln f 1 -> 2^-20, "
+                     "80% flat, exchange every 10^4 trials)"),
+    "c3": (C3, 192, "32x32 periodic Ising 2D-REWL (16 windows x 8 walkers, overlap 3/4, ln f 1 -> 2^-24, "
+                    "80% flat, exchange every 10^4 trials)"),
+    "c4": (C4, 16, "64x64 periodic Ising 2D-REWL (64 windows x 4 walkers, overlap 3/4, ln f 1 -> 2^-20, "
+                   "80% flat, exchange every 10^5 trials)"),
+}
 # Algorithmic VALU issue slots per trial (full-rate 32-bit lane operations; a
 # 32x32->64 multiply counts 4): derivation in the design notes.
 VALU_SLOTS_PER_TRIAL = 133
@@ -40,8 +51,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def problems(R, R_mod):
-    return [R_mod.Problem(seed=s, **C2) for s in range(R)]
+def problems(R, R_mod, cfg=C2):
+    return [R_mod.Problem(seed=s, **cfg) for s in range(R)]
 
 
 def time_plan(R, plan, steps, warmup):
@@ -56,16 +67,54 @@ def time_plan(R, plan, steps, warmup):
     return time.perf_counter() - t0
 
 
+def bench_lnz(R, torch, np):
+    """ln Z forward and first-order backward (moments + grad ln g) on the 32x32 joint table shaped
+    as the exact marginal g(E) (stored in tests/golden) times the binomial in M, over the grid
+    beta in [0.1, 1] (1024 points) x h in [-0.5, 0.5] (256 points)."""
+    import math
+    N = 1024
+    with open(os.path.join(ROOT, "tests", "golden", "exact_lngE.json")) as f:
+        lge = np.array([-math.inf if v is None else v for v in json.load(f)["lattices"]["32"]["lnge"]])
+    lbin = np.array([math.lgamma(N + 1) - math.lgamma(k + 1) - math.lgamma(N - k + 1) for k in range(N + 1)])
+    lng = lge[:, None] + lbin[None, :] - N * math.log(2.0)
+    b = np.linspace(0.1, 1.0, 1024)
+    h = np.linspace(-0.5, 0.5, 256)
+    B, Hh = np.meshgrid(b, h, indexing="ij")
+    dl = torch.tensor(lng, device="cuda")
+    db = torch.tensor(B.ravel(), device="cuda")
+    dh = torch.tensor(Hh.ravel(), device="cuda")
+    go = torch.ones_like(db)
+    terms = db.numel() * int(np.isfinite(lng).sum())
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    R.lnz_forward(dl, db, dh, N)                       # warm-up
+    torch.cuda.synchronize()
+    ev[0].record()
+    z = R.lnz_forward(dl, db, dh, N)
+    ev[1].record()
+    gb, gh, gl = R._lnz_grads(dl, db, dh, z, go, N, 0, 0, True)
+    ev[2].record()
+    torch.cuda.synchronize()
+    fwd = ev[0].elapsed_time(ev[1])
+    bwd = ev[1].elapsed_time(ev[2])
+    return {"table": "1025 x 1025 bins (synthetic 32x32-shaped)", "grid": int(db.numel()),
+            "finite_bins": int(np.isfinite(lng).sum()), "forward_ms": fwd, "backward_ms": bwd,
+            "forward_terms_per_s": terms / (fwd * 1e-3),
+            "backward_terms_per_s": terms / (bwd * 1e-3), "dtype": "f64"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--replicas", type=int, default=4096)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--replicas", type=int, default=0, help="independent problems (0 = the workload's default)")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--cpu-intervals", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-lnz", action="store_true")
     ap.add_argument("--wg", type=int, default=0, help="walkers per workgroup (0 = library's choice)")
     ap.add_argument("--grid-waves", type=int, default=0, help="persistent grid waves per CU (0 = library's choice)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -92,15 +141,25 @@ def main():
 
     dev = "cuda:0"
     K, W = args.steps, args.warmup
-    X = C2["interval"]
+    cfg, default_r, wl_text = WORKLOADS[args.workload]
+    if args.replicas <= 0:
+        args.replicas = default_r
+    X = cfg["interval"]
+    n1 = cfg["n_windows"] * cfg["walkers_per_window"]
 
     # ---------------- batched form on the replica batch (the headline value)
-    log(f"[bench] batched: {args.replicas} replicas of the 16x16 REWL problem, init ...")
+    log(f"[bench] batched: {args.replicas} replicas of the {cfg['L']}x{cfg['L']} REWL problem, init ...")
     tuning = R.Tuning(graph_intervals=K, walkers_per_wg=args.wg, grid_waves_per_cu=args.grid_waves)
-    plan = R.Plan(problems(args.replicas, R), tuning, device=dev)
+    plan = R.Plan(problems(args.replicas, R, cfg), tuning, device=dev)
     t0 = time.perf_counter()
     plan.init()
     log(f"[bench] init + window entry {time.perf_counter() - t0:.2f}s; warmup {W}, timed {K} steps")
+    tuned = "fixed"
+    if not args.no_autotune and args.wg == 0 and args.grid_waves == 0:
+        from paper_1508_02748_amd.tune import autotune
+        best = autotune(plan, intervals=1, use_cache=False)
+        tuned = f"autotuned: walkers_per_wg={best.walkers_per_wg}, grid_waves_per_cu={best.grid_waves_per_cu}"
+        log(f"[bench] {tuned}")
     # timed region: the batched launch sequence enqueued eagerly with a HIP
     # event pair around every sweep kernel on the plan's stream
     plan.set_profile(True)
@@ -128,47 +187,50 @@ def main():
     if not args.no_plain:
         Kp = args.plain_steps
         log(f"[bench] plain vs batched on one problem, {Kp} intervals each")
-        pp = R.Plan(problems(1, R), R.Tuning(form=R.FORM_PLAIN), device=dev)
+        pp = R.Plan(problems(1, R, cfg), R.Tuning(form=R.FORM_PLAIN), device=dev)
         pp.init()
         Tp = time_plan(1, pp, Kp, 1)
-        pb = R.Plan(problems(1, R), R.Tuning(graph_intervals=Kp), device=dev)
+        pb = R.Plan(problems(1, R, cfg), R.Tuning(graph_intervals=Kp), device=dev)
         pb.init()
         Tb = time_plan(1, pb, Kp, 1)
         same = all((pp.walker(0, w, a)["lng"] == pb.walker(0, w, a)["lng"]).all()
-                   for w in range(C2["n_windows"]) for a in range(C2["walkers_per_window"]))
-        n1 = C2["n_windows"] * C2["walkers_per_window"]
-        plain = {"workload": "one 16x16 REWL problem (32 walkers)", "intervals": Kp,
+                   for w in range(cfg["n_windows"]) for a in range(cfg["walkers_per_window"]))
+        plain = {"workload": f"one {cfg['L']}x{cfg['L']} REWL problem ({n1} walkers)", "intervals": Kp,
                  "plain_value": n1 * X * Kp / Tp, "batched_value": n1 * X * Kp / Tb,
                  "speedup": Tp / Tb, "identical_final_state": bool(same),
                  "batched_replicas_speedup_vs_plain": value / (n1 * X * Kp / Tp)}
         log(f"[bench] plain {plain['plain_value']:.3e}, batched(1) {plain['batched_value']:.3e} trials/s")
         del pp, pb
 
+    # ---------------- reweighting ln Z(beta, h) and its backward on the 32x32 size
+    lnz = None
+    if not args.no_lnz:
+        lnz = bench_lnz(R, torch, np)
+        log(f"[bench] lnZ forward {lnz['forward_ms']:.1f} ms, backward {lnz['backward_ms']:.1f} ms")
+
     # ---------------- CPU oracle on the host cores (bounded sample)
     cpu = None
     if not args.no_cpu:
         from oracle.rewl import OracleREWL
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        o = OracleREWL(seed=0, **{"L": 16, "n_windows": 8, "overlap": (3, 4), "walkers_per_window": 4,
-                                  "k_final": 20, "flat": (4, 5), "interval": X})
+        o = OracleREWL(seed=0, **cfg)
         o.init()
-        n = args.cpu_intervals
-        log(f"[bench] oracle: {n} intervals of one 16x16 REWL problem on {threads} threads")
+        n = args.cpu_intervals if args.workload == "c2" else max(1, args.cpu_intervals // 30)
+        log(f"[bench] oracle: {n} intervals of one {cfg['L']}x{cfg['L']} REWL problem on {threads} threads")
         t0 = time.perf_counter()
         o.run(n)
         Tc = time.perf_counter() - t0
-        cpu = {"value": 32 * X * n / Tc, "unit": "spin-flip attempts/s", "cores": min(threads, 32),
+        cpu = {"value": n1 * X * n / Tc, "unit": "spin-flip attempts/s", "cores": min(threads, n1),
                "kind": "oracle",
-               "sample": f"{n} intervals (10^4 trials x 32 walkers each) of one 16x16 REWL problem, seed 0; "
-                         f"{Tc:.1f} s"}
+               "sample": f"{n} intervals ({X} trials x {n1} walkers each) of one {cfg['L']}x{cfg['L']} REWL "
+                         f"problem, seed 0; {Tc:.1f} s"}
 
     out = {
         "metric": METRIC, "value": value, "unit": "spin-flip attempts/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": T / K * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-        "config": {"workload": f"16x16 periodic Ising 2D-REWL (8 windows x 4 walkers, overlap 3/4, "
-                               f"ln f 1 -> 2^-20, 80% flat, exchange every 10^4 trials) x {args.replicas} "
-                               f"independent replicas, batched form",
+        "config": {"workload": f"{wl_text} x {args.replicas} independent replicas, batched form",
+                   "tuning": tuned,
                    "replicas": args.replicas, "walkers": n_walk, "trials_per_walker_per_step": X,
                    "stage_range": list(stages), "parallelism": "one walker per lane",
                    "graph_replay_value": trials / Tg},
@@ -178,6 +240,7 @@ def main():
                      "slots_per_trial": VALU_SLOTS_PER_TRIAL},
         "cpu_baseline": cpu,
         "plain": plain,
+        "lnz": lnz,
     }
     print(json.dumps(out), flush=True)
 

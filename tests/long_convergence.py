@@ -1,0 +1,127 @@
+"""Long GPU runs to convergence, compared with the exact g(E) (not a pytest file).
+
+Runs REWL problems on the GPU until every problem has finished its last stage
+(resumable across calls through rewl_save / rewl_load checkpoints), joins each
+problem's fragments on the device (Eq. 3, Eq. 4) and compares the marginal
+ln g(E) with the exact finite-lattice values stored in tests/golden/ (Sec. 3,
+Fig. 5):  epsilon(E) = |ln g - ln g_exact| / ln g_exact over realizable E.
+
+  python tests/long_convergence.py --config c2 --replicas 8 --seconds 900 --out gpurun_out/conv_c2
+  python tests/long_convergence.py --config c2 ... --resume      # continue from the checkpoint
+
+Configurations: c2 = 16x16, 8 windows (overlap 3/4) x 4 walkers, ln f -> 2^-20;
+p8w2 / p8w20 = 8x8, 3 windows (overlap 1/2) x 2 or 20 walkers, ln f -> 2^-20.
+Replica r uses seed r.  Progress is printed every minute.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+import zlib
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+CONFIGS = {
+    "c2": dict(L=16, n_windows=8, overlap=(3, 4), walkers_per_window=4, k_final=20, interval=10_000),
+    "p8w2": dict(L=8, n_windows=3, overlap=(1, 2), walkers_per_window=2, k_final=20, interval=10_000),
+    "p8w20": dict(L=8, n_windows=3, overlap=(1, 2), walkers_per_window=20, k_final=20, interval=10_000),
+}
+
+
+def exact_lnge(L):
+    with open(os.path.join(ROOT, "tests", "golden", "exact_lngE.json")) as f:
+        ent = json.load(f)["lattices"][str(L)]
+    return np.array([-math.inf if v is None else v for v in ent["lnge"]])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--replicas", type=int, default=8)
+    ap.add_argument("--seconds", type=float, default=900)
+    ap.add_argument("--out", default="gpurun_out/conv")
+    ap.add_argument("--resume", action="store_true")
+    args = ap.parse_args()
+    import torch
+    import paper_1508_02748_amd as R
+
+    os.makedirs(args.out, exist_ok=True)
+    cfg = CONFIGS[args.config]
+    probs = [R.Problem(seed=s, **cfg) for s in range(args.replicas)]
+    plan = R.Plan(probs, R.Tuning(graph_intervals=64))
+    ck = os.path.join(args.out, "checkpoint.z")
+    meta_path = os.path.join(args.out, "progress.json")
+    meta = {"intervals": 0, "seconds": 0.0}
+    if args.resume and os.path.exists(ck):
+        with open(ck, "rb") as f:
+            plan.load(zlib.decompress(f.read()))
+        with open(meta_path) as f:
+            meta = json.load(f)
+        print(f"resumed at {meta['intervals']} intervals", flush=True)
+    else:
+        plan.init()
+    t0 = time.time()
+    last = t0
+    while time.time() - t0 < args.seconds:
+        plan.run(256)
+        meta["intervals"] += 256
+        q = plan.query()
+        if q["done"].all():
+            break
+        if time.time() - last > 60:
+            last = time.time()
+            print(f"[{args.config}] {meta['intervals']} intervals, stages {int(q['stage'].min())}..{int(q['stage'].max())}, "
+                  f"{int(q['done'].sum())}/{len(probs)} done, {time.time() - t0:.0f}s", flush=True)
+    meta["seconds"] += time.time() - t0
+    q = plan.query()
+    meta["done"] = int(q["done"].sum())
+    meta["stage"] = [int(x) for x in q["stage"]]
+    meta["trials_per_walker"] = [int(x) for x in q["trials"]]
+    if not q["done"].all():
+        with open(ck, "wb") as f:
+            f.write(zlib.compress(plan.save(), 6))
+        with open(meta_path, "w") as f:
+            json.dump(meta, f)
+        print(f"checkpoint written: {meta['intervals']} intervals, {meta['done']}/{len(probs)} done", flush=True)
+        return
+    ex = exact_lnge(cfg["L"])
+    ok = np.isfinite(ex) & (ex > 0)
+    res = {"config": args.config, "problem": {k: list(v) if isinstance(v, tuple) else v for k, v in cfg.items()},
+           "replicas": args.replicas, **meta, "per_replica": []}
+    margs = []
+    for i in range(len(probs)):
+        out = {}
+        for norm in ("ground", "sum"):
+            _, g, em = plan.merge(i, norm)
+            g = g.cpu().numpy()
+            eps = np.abs(g[ok] - ex[ok]) / ex[ok]
+            out[norm] = {"max_eps": float(eps.max()), "mean_eps": float(eps.mean()),
+                         "max_abs": float(np.max(np.abs(g[ok] - ex[ok]))), "e_mat": em}
+            if norm == "sum":
+                margs.append(g)
+        res["per_replica"].append(out)
+        print(f"replica {i}: max eps ground {out['ground']['max_eps']:.4g} sum {out['sum']['max_eps']:.4g}", flush=True)
+    # mean over replicas and jackknife error of that mean (sum normalisation)
+    M = np.array(margs)[:, ok]
+    n = M.shape[0]
+    mean = M.mean(0)
+    jk = np.array([(M.sum(0) - M[k]) / (n - 1) for k in range(n)])
+    err = np.sqrt((n - 1) / n * ((jk - jk.mean(0)) ** 2).sum(0))
+    eps_mean = np.abs(mean - ex[ok]) / ex[ok]
+    res["replica_mean"] = {"max_eps": float(eps_mean.max()), "mean_eps": float(eps_mean.mean()),
+                           "max_jackknife_err": float(err.max()),
+                           "max_abs_over_err": float(np.max(np.abs(mean - ex[ok]) / np.maximum(err, 1e-300)))}
+    with open(os.path.join(args.out, "result.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    if os.path.exists(ck):
+        os.remove(ck)
+    print(json.dumps(res["replica_mean"]), flush=True)
+
+
+if __name__ == "__main__":
+    main()

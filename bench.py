@@ -45,6 +45,10 @@ WORKLOADS = {
 VALU_SLOTS_PER_TRIAL = 133
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz full-rate VALU lane operations per second.
 VALU_PEAK_SLOTS = 256 * 64 * 2.4e9
+# HBM-side bytes per sweep launch, FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a 1 GiB
+# device copy), by (workload, replicas, walkers per workgroup, grid waves per CU); measured on
+# the current sweep kernel with rocprofv3 --pmc.  Other shapes report null.
+TRAFFIC_BYTES = {("c2", 4096, 256, 4): 38.03e9}
 
 
 def log(*a):
@@ -111,7 +115,7 @@ def main():
     ap.add_argument("--replicas", type=int, default=0, help="independent problems (0 = the workload's default)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=5)
-    ap.add_argument("--cpu-intervals", type=int, default=300)
+    ap.add_argument("--cpu-intervals", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-lnz", action="store_true")
@@ -155,11 +159,14 @@ def main():
     plan.init()
     log(f"[bench] init + window entry {time.perf_counter() - t0:.2f}s; warmup {W}, timed {K} steps")
     tuned = "fixed"
+    shape = (args.wg, args.grid_waves)
     if not args.no_autotune and args.wg == 0 and args.grid_waves == 0:
         from paper_1508_02748_amd.tune import autotune
         best = autotune(plan, intervals=1, use_cache=False)
+        shape = (best.walkers_per_wg, best.grid_waves_per_cu)
         tuned = f"autotuned: walkers_per_wg={best.walkers_per_wg}, grid_waves_per_cu={best.grid_waves_per_cu}"
         log(f"[bench] {tuned}")
+    traffic = TRAFFIC_BYTES.get((args.workload, args.replicas) + shape)
     # timed region: the batched launch sequence enqueued eagerly with a HIP
     # event pair around every sweep kernel on the plan's stream
     plan.set_profile(True)
@@ -236,7 +243,8 @@ def main():
                    "graph_replay_value": trials / Tg},
         "roofline": {"bound": "alu", "achieved": achieved_slots / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                      "unit": "Tslot/s (full-rate VALU lane-ops)", "frac": achieved_slots / VALU_PEAK_SLOTS,
-                     "traffic": None, "kernel": "k_sweep", "kernel_ms": sweep_avg,
+                     "traffic": traffic, "traffic_unit": "HBM bytes per sweep launch (rocprofv3 FETCH_SIZE, WRITE_SIZE)",
+                     "kernel": "k_sweep", "kernel_ms": sweep_avg,
                      "slots_per_trial": VALU_SLOTS_PER_TRIAL},
         "cpu_baseline": cpu,
         "plain": plain,

@@ -10,8 +10,12 @@ Fig. 5):  epsilon(E) = |ln g - ln g_exact| / ln g_exact over realizable E.
   python tests/long_convergence.py --config c2 ... --resume      # continue from the checkpoint
 
 Configurations: c2 = 16x16, 8 windows (overlap 3/4) x 4 walkers, ln f -> 2^-20;
-p8w2 / p8w20 = 8x8, 3 windows (overlap 1/2) x 2 or 20 walkers, ln f -> 2^-20.
-Replica r uses seed r.  Progress is printed every minute.
+p8w2 / p8w20 = 8x8, 3 windows (overlap 1/2) x 2 or 20 walkers, ln f -> 2^-20;
+p8pair = 8x8 serial 2D-WL (one walker over the whole (E, M) space) next to
+8x8 2D-REWL (3 windows, overlap 1/2, 3 walkers), both to ln f = 2^-20, with
+the relative difference of Eq. 5 between the two joint densities of states
+(Sec. 3, Fig. 4(b)).  Replica r uses seed r (the serial runs of p8pair use
+seed 1000 + r).  Progress is printed every minute.
 """
 import argparse
 import json
@@ -26,10 +30,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
+P8 = dict(L=8, overlap=(1, 2), k_final=20, interval=10_000)
 CONFIGS = {
-    "c2": dict(L=16, n_windows=8, overlap=(3, 4), walkers_per_window=4, k_final=20, interval=10_000),
-    "p8w2": dict(L=8, n_windows=3, overlap=(1, 2), walkers_per_window=2, k_final=20, interval=10_000),
-    "p8w20": dict(L=8, n_windows=3, overlap=(1, 2), walkers_per_window=20, k_final=20, interval=10_000),
+    "c2": [dict(L=16, n_windows=8, overlap=(3, 4), walkers_per_window=4, k_final=20, interval=10_000)],
+    "p8w2": [dict(P8, n_windows=3, walkers_per_window=2)],
+    "p8w20": [dict(P8, n_windows=3, walkers_per_window=20)],
+    "p8pair": [dict(P8, n_windows=3, walkers_per_window=3), dict(P8, n_windows=1, walkers_per_window=1)],
 }
 
 
@@ -37,6 +43,11 @@ def exact_lnge(L):
     with open(os.path.join(ROOT, "tests", "golden", "exact_lngE.json")) as f:
         ent = json.load(f)["lattices"][str(L)]
     return np.array([-math.inf if v is None else v for v in ent["lnge"]])
+
+
+def rel_diff(a, b):
+    """Eq. 5 from logarithms: |g1 - g2| / ((g1 + g2) / 2) = 2 |tanh((ln g1 - ln g2) / 2)|."""
+    return 2.0 * np.abs(np.tanh(0.5 * (a - b)))
 
 
 def main():
@@ -47,12 +58,16 @@ def main():
     ap.add_argument("--out", default="gpurun_out/conv")
     ap.add_argument("--resume", action="store_true")
     args = ap.parse_args()
-    import torch
+    import torch  # noqa: F401  (device memory for the plan)
     import paper_1508_02748_amd as R
 
     os.makedirs(args.out, exist_ok=True)
-    cfg = CONFIGS[args.config]
-    probs = [R.Problem(seed=s, **cfg) for s in range(args.replicas)]
+    groups = CONFIGS[args.config]
+    probs, tags = [], []
+    for gi, cfg in enumerate(groups):
+        for r in range(args.replicas):
+            probs.append(R.Problem(seed=1000 * gi + r, **cfg))
+            tags.append((gi, r))
     plan = R.Plan(probs, R.Tuning(graph_intervals=64))
     ck = os.path.join(args.out, "checkpoint.z")
     meta_path = os.path.join(args.out, "progress.json")
@@ -89,33 +104,55 @@ def main():
             json.dump(meta, f)
         print(f"checkpoint written: {meta['intervals']} intervals, {meta['done']}/{len(probs)} done", flush=True)
         return
-    ex = exact_lnge(cfg["L"])
+    L = groups[0]["L"]
+    ex = exact_lnge(L)
     ok = np.isfinite(ex) & (ex > 0)
-    res = {"config": args.config, "problem": {k: list(v) if isinstance(v, tuple) else v for k, v in cfg.items()},
+    res = {"config": args.config,
+           "problems": [{k: list(v) if isinstance(v, tuple) else v for k, v in c.items()} for c in groups],
            "replicas": args.replicas, **meta, "per_replica": []}
-    margs = []
-    for i in range(len(probs)):
-        out = {}
+    margs = {gi: [] for gi in range(len(groups))}
+    joints = {}
+    for i, (gi, r) in enumerate(tags):
+        out = {"group": gi, "replica": r}
         for norm in ("ground", "sum"):
-            _, g, em = plan.merge(i, norm)
+            jt, g, em = plan.merge(i, norm)
             g = g.cpu().numpy()
             eps = np.abs(g[ok] - ex[ok]) / ex[ok]
             out[norm] = {"max_eps": float(eps.max()), "mean_eps": float(eps.mean()),
                          "max_abs": float(np.max(np.abs(g[ok] - ex[ok]))), "e_mat": em}
             if norm == "sum":
-                margs.append(g)
+                margs[gi].append(g)
+                joints[(gi, r)] = jt.cpu().numpy()
         res["per_replica"].append(out)
-        print(f"replica {i}: max eps ground {out['ground']['max_eps']:.4g} sum {out['sum']['max_eps']:.4g}", flush=True)
-    # mean over replicas and jackknife error of that mean (sum normalisation)
-    M = np.array(margs)[:, ok]
-    n = M.shape[0]
-    mean = M.mean(0)
-    jk = np.array([(M.sum(0) - M[k]) / (n - 1) for k in range(n)])
-    err = np.sqrt((n - 1) / n * ((jk - jk.mean(0)) ** 2).sum(0))
-    eps_mean = np.abs(mean - ex[ok]) / ex[ok]
-    res["replica_mean"] = {"max_eps": float(eps_mean.max()), "mean_eps": float(eps_mean.mean()),
-                           "max_jackknife_err": float(err.max()),
-                           "max_abs_over_err": float(np.max(np.abs(mean - ex[ok]) / np.maximum(err, 1e-300)))}
+        print(f"group {gi} replica {r}: max eps ground {out['ground']['max_eps']:.4g} sum {out['sum']['max_eps']:.4g}",
+              flush=True)
+    # mean over replicas and jackknife error of that mean (sum normalisation), per group
+    res["replica_mean"] = []
+    for gi in range(len(groups)):
+        M = np.array(margs[gi])[:, ok]
+        n = M.shape[0]
+        mean = M.mean(0)
+        jk = np.array([(M.sum(0) - M[k]) / (n - 1) for k in range(n)])
+        err = np.sqrt((n - 1) / n * ((jk - jk.mean(0)) ** 2).sum(0))
+        eps_mean = np.abs(mean - ex[ok]) / ex[ok]
+        res["replica_mean"].append({"group": gi, "max_eps": float(eps_mean.max()), "mean_eps": float(eps_mean.mean()),
+                                    "max_jackknife_err": float(err.max()),
+                                    "max_abs_over_err": float(np.max(np.abs(mean - ex[ok]) / np.maximum(err, 1e-300)))})
+    if len(groups) == 2:
+        # Eq. 5 between the REWL (group 0) and serial WL (group 1) joint DOS of each replica pair
+        diffs = []
+        for r in range(args.replicas):
+            a, b = joints[(0, r)], joints[(1, r)]
+            both = np.isfinite(a) & np.isfinite(b)
+            d = rel_diff(a[both], b[both])
+            e_rows = np.nonzero(both)[0]
+            edge = (e_rows <= 2) | (e_rows >= L * L - 2)
+            diffs.append({"replica": r, "bins": int(both.sum()),
+                          "only_one": int((np.isfinite(a) ^ np.isfinite(b)).sum()),
+                          "max": float(d.max()), "mean": float(d.mean()), "median": float(np.median(d)),
+                          "mean_interior": float(d[~edge].mean()), "mean_edges": float(d[edge].mean())})
+            print(f"replica {r}: Eq. 5 over {both.sum()} bins: mean {d.mean():.4g}, max {d.max():.4g}", flush=True)
+        res["rel_diff"] = diffs
     with open(os.path.join(args.out, "result.json"), "w") as f:
         json.dump(res, f, indent=1)
     if os.path.exists(ck):

@@ -100,10 +100,27 @@ def bench_lnz(R, torch, np):
     torch.cuda.synchronize()
     fwd = ev[0].elapsed_time(ev[1])
     bwd = ev[1].elapsed_time(ev[2])
+    # the same grid as a tensor product (factorised through the M columns)
+    dbv, dhv = torch.tensor(b, device="cuda"), torch.tensor(h, device="cuda")
+    gov = torch.ones((b.size, h.size), dtype=torch.float64, device="cuda")
+    R.lnz_grid_forward(dl, dbv, dhv, N)                # warm-up
+    torch.cuda.synchronize()
+    ev[0].record()
+    zg = R.lnz_grid_forward(dl, dbv, dhv, N)
+    ev[1].record()
+    R.lnz_grid_backward(dl, dbv, dhv, zg, gov, N, want_lng=True)
+    ev[2].record()
+    torch.cuda.synchronize()
+    gfwd = ev[0].elapsed_time(ev[1])
+    gbwd = ev[1].elapsed_time(ev[2])
+    agree = float((zg.reshape(-1) - z).abs().max())
     return {"table": "1025 x 1025 bins (synthetic 32x32-shaped)", "grid": int(db.numel()),
             "finite_bins": int(np.isfinite(lng).sum()), "forward_ms": fwd, "backward_ms": bwd,
             "forward_terms_per_s": terms / (fwd * 1e-3),
-            "backward_terms_per_s": terms / (bwd * 1e-3), "dtype": "f64"}
+            "backward_terms_per_s": terms / (bwd * 1e-3),
+            "grid_forward_ms": gfwd, "grid_backward_ms": gbwd,
+            "grid_forward_terms_per_s": terms / (gfwd * 1e-3),
+            "grid_vs_direct_max_abs_diff": agree, "dtype": "f64"}
 
 
 def main():
@@ -213,7 +230,8 @@ def main():
     lnz = None
     if not args.no_lnz:
         lnz = bench_lnz(R, torch, np)
-        log(f"[bench] lnZ forward {lnz['forward_ms']:.1f} ms, backward {lnz['backward_ms']:.1f} ms")
+        log(f"[bench] lnZ forward {lnz['forward_ms']:.1f} ms, backward {lnz['backward_ms']:.1f} ms; "
+            f"tensor-product grid forward {lnz['grid_forward_ms']:.2f} ms, backward {lnz['grid_backward_ms']:.2f} ms")
 
     # ---------------- CPU oracle on the host cores (bounded sample)
     cpu = None

@@ -188,6 +188,36 @@ rewl_status rewl_lnz_backward(const double* lng, int32_t N, int32_t e0, int32_t 
                               double* grad_beta, double* grad_h, double* grad_lng,
                               double* mom, int32_t order, void* hip_stream);
 
+/* Reweighting on a tensor-product grid beta[0..nB) x h[0..nH): lnz[i*nH + j]
+ * = ln Z(beta[i], h[j]), the same quantity as rewl_lnz_forward at those
+ * points (equal up to the order of rounding).  The sum is factorised through
+ * the M columns: A(i, M) = log sum_E exp(ln g - beta_i E) does not depend on
+ * h, and ln Z = log sum_M exp(A(i, M) + beta_i h_j M); this needs
+ * nB nE nM + nB nH nM exponentials instead of nB nH nE nM.  Geometry as for
+ * rewl_lnz_forward; all arrays are device memory; `workspace` holds
+ * rewl_lnz_grid_workspace_size bytes (caller-owned, contents not kept
+ * between calls).  nB <= 65535.  Enqueued on hip_stream. */
+rewl_status rewl_lnz_grid_workspace_size(int32_t nM, int64_t nB, int64_t nH, size_t* bytes);
+rewl_status rewl_lnz_grid_forward(const double* lng, int32_t N, int32_t e0, int32_t nE,
+                                  int32_t m0, int32_t nM, const double* beta, int64_t nB,
+                                  const double* h, int64_t nH, void* workspace, size_t workspace_bytes,
+                                  double* lnz, void* hip_stream);
+
+/* Backward of rewl_lnz_grid_forward with the saved lnz (nB x nH) and upstream
+ * grad_out (nB x nH, NULL = all ones).  grad_beta (nB) = sum_j g_ij <-E + h_j M>_ij
+ * and grad_h (nH) = sum_i g_ij beta_i <M>_ij (both or neither); grad_lng
+ * (nE x nM, nullable) = sum_ij g_ij p_ij(E, M); mom (nullable, nB x nH x 5)
+ * = <M>, <U>, Var(U), Var(M), Cov(U, M) per point, U = -E + h M, as in
+ * rewl_lnz_backward order 2.  Variances use the law of total variance over
+ * the M columns, with central sums throughout.  At least one output is
+ * required. */
+rewl_status rewl_lnz_grid_backward(const double* lng, int32_t N, int32_t e0, int32_t nE,
+                                   int32_t m0, int32_t nM, const double* beta, int64_t nB,
+                                   const double* h, int64_t nH, const double* lnz,
+                                   const double* grad_out, void* workspace, size_t workspace_bytes,
+                                   double* grad_beta, double* grad_h, double* grad_lng, double* mom,
+                                   void* hip_stream);
+
 /* Replace the tuning of a plan (same form); results do not change. */
 rewl_status rewl_set_tuning(rewl_plan* plan, const rewl_tuning* tuning);
 

@@ -75,6 +75,11 @@ def lib():
                                   P, P], C.c_int),
             "rewl_lnz_backward": ([P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_int64,
                                    P, P, P, P, P, P, C.c_int32, P], C.c_int),
+            "rewl_lnz_grid_workspace_size": ([C.c_int32, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)], C.c_int),
+            "rewl_lnz_grid_forward": ([P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, C.c_int64,
+                                       P, C.c_int64, P, C.c_size_t, P, P], C.c_int),
+            "rewl_lnz_grid_backward": ([P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, C.c_int64,
+                                        P, C.c_int64, P, P, P, C.c_size_t, P, P, P, P, P], C.c_int),
             "rewl_sweep_times": ([P, P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
             "rewl_set_profile": ([P, C.c_int32], C.c_int),
             "rewl_merge_workspace_size": ([P, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
@@ -309,6 +314,45 @@ def _lnz_grads(lng, beta, h, lnz, grad_out, N, e0, m0, want_lng):
     return gb, gh, gl
 
 
+def _grid_ws(lng, nB, nH):
+    import torch
+    nb = C.c_size_t()
+    _check(lib().rewl_lnz_grid_workspace_size(lng.shape[1], nB, nH, C.byref(nb)))
+    return torch.empty(max(1, nb.value), dtype=torch.uint8, device=lng.device), nb.value
+
+
+def lnz_grid_forward(lng, beta, h, N, e0=0, m0=0):
+    """ln Z on the tensor-product grid beta (nB) x h (nH): (nB, nH) float64 on the device."""
+    import torch
+    assert lng.dtype == torch.float64 and lng.is_cuda and lng.is_contiguous()
+    beta = beta.contiguous()
+    h = h.contiguous()
+    out = torch.empty((beta.numel(), h.numel()), dtype=torch.float64, device=lng.device)
+    ws, nb = _grid_ws(lng, beta.numel(), h.numel())
+    st = torch.cuda.current_stream(lng.device).cuda_stream
+    _check(lib().rewl_lnz_grid_forward(_ptr(lng), *_geom(lng, N, e0, m0), _ptr(beta), beta.numel(), _ptr(h),
+                                       h.numel(), _ptr(ws), nb, _ptr(out), C.c_void_p(st)))
+    return out
+
+
+def lnz_grid_backward(lng, beta, h, lnz, grad_out, N, e0=0, m0=0, want_grads=True, want_lng=False,
+                      want_mom=False):
+    """(grad_beta (nB), grad_h (nH), grad_lng or None, moments (nB, nH, 5) or None) on the device."""
+    import torch
+    nB, nH = beta.numel(), h.numel()
+    gb = torch.empty(nB, dtype=torch.float64, device=lng.device) if want_grads else None
+    gh = torch.empty(nH, dtype=torch.float64, device=lng.device) if want_grads else None
+    gl = torch.empty_like(lng) if want_lng else None
+    mom = torch.empty((nB, nH, 5), dtype=torch.float64, device=lng.device) if want_mom else None
+    go = None if grad_out is None else grad_out.contiguous()
+    ws, nb = _grid_ws(lng, nB, nH)
+    st = torch.cuda.current_stream(lng.device).cuda_stream
+    _check(lib().rewl_lnz_grid_backward(_ptr(lng), *_geom(lng, N, e0, m0), _ptr(beta.contiguous()), nB,
+                                        _ptr(h.contiguous()), nH, _ptr(lnz.contiguous()), _ptr(go), _ptr(ws), nb,
+                                        _ptr(gb), _ptr(gh), _ptr(gl), _ptr(mom), C.c_void_p(st)))
+    return gb, gh, gl, mom
+
+
 def _torch_functions():
     import torch
 
@@ -360,7 +404,56 @@ def _torch_functions():
             gb, gh = _LnZBackward.apply(grad_out, beta, h, lng.detach(), lnz.detach(), N, e0, m0)
             return g_lng, gb, gh, None, None, None
 
-    return LnZ
+    class _LnZGridBackward(torch.autograd.Function):
+        """(grad_out (nB, nH), beta, h) -> (grad_beta (nB), grad_h (nH)), differentiable once more."""
+
+        @staticmethod
+        def forward(ctx, grad_out, beta, h, lng, lnz, N, e0, m0):
+            gb, gh, _, _ = lnz_grid_backward(lng, beta, h, lnz, grad_out, N, e0, m0)
+            ctx.save_for_backward(grad_out, beta, h, lng, lnz)
+            ctx.geo = (N, e0, m0)
+            return gb, gh
+
+        @staticmethod
+        def backward(ctx, a, b):
+            grad_out, beta, h, lng, lnz = ctx.saved_tensors
+            N, e0, m0 = ctx.geo
+            _, _, _, mom = lnz_grid_backward(lng, beta, h, lnz, None, N, e0, m0, want_grads=False, want_mom=True)
+            mM, mU, vU, vM, cUM = mom.unbind(2)
+            a = torch.zeros_like(beta) if a is None else a
+            b = torch.zeros_like(h) if b is None else b
+            bi = beta[:, None]
+            cross = mM + bi * cUM
+            d_go = a[:, None] * mU + b[None, :] * bi * mM
+            d_beta = (grad_out * (a[:, None] * vU + b[None, :] * cross)).sum(1)
+            d_h = (grad_out * (a[:, None] * cross + b[None, :] * bi * bi * vM)).sum(0)
+            return d_go, d_beta, d_h, None, None, None, None, None
+
+    class LnZGrid(torch.autograd.Function):
+        """ln Z on a tensor-product grid: (lng, beta (nB), h (nH), N) -> (nB, nH).
+
+        Same quantity and derivatives as LnZ at the points (beta_i, h_j),
+        computed through the factorisation over M columns."""
+
+        @staticmethod
+        def forward(ctx, lng, beta, h, N, e0=0, m0=0):
+            lnz = lnz_grid_forward(lng, beta, h, N, e0, m0)
+            ctx.save_for_backward(lng, beta, h, lnz)
+            ctx.geo = (N, e0, m0)
+            return lnz
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            lng, beta, h, lnz = ctx.saved_tensors
+            N, e0, m0 = ctx.geo
+            g_lng = None
+            if ctx.needs_input_grad[0]:
+                _, _, g_lng, _ = lnz_grid_backward(lng, beta.detach(), h.detach(), lnz, grad_out.detach(), N, e0,
+                                                   m0, want_grads=False, want_lng=True)
+            gb, gh = _LnZGridBackward.apply(grad_out, beta, h, lng.detach(), lnz.detach(), N, e0, m0)
+            return g_lng, gb, gh, None, None, None
+
+    return LnZ, LnZGrid
 
 
 _LnZ = None
@@ -371,4 +464,12 @@ def LnZ():
     global _LnZ
     if _LnZ is None:
         _LnZ = _torch_functions()
-    return _LnZ
+    return _LnZ[0]
+
+
+def LnZGrid():
+    """The torch.autograd.Function computing ln Z on a tensor-product (beta, h) grid."""
+    global _LnZ
+    if _LnZ is None:
+        _LnZ = _torch_functions()
+    return _LnZ[1]

@@ -175,6 +175,270 @@ __global__ void __launch_bounds__(TILE) k_lnz_glng(Geo geo, const double* beta, 
     if (i < nb) glng[i] = acc;
 }
 
+
+// ------------------------------------------------------------------ tensor-product grids
+// For a grid beta_i x h_j the sum factorises through the M columns:
+//   A(i, M)  = log sum_E exp(ln g(E, M) - beta_i E)            (independent of h)
+//   ln Z(i,j) = log sum_M exp(A(i, M) + beta_i h_j M)
+// so the exponentials cost nB nE nM + nB nH nM instead of nB nH nE nM.  The
+// backward needs, per column, the conditional mean and variance of E at
+// beta_i (law of total variance), and for d/d ln g the column weights
+//   c(i, M) = sum_j grad_out(i,j) exp(A(i, M) + beta_i h_j M - ln Z(i,j)),
+// so that d ln Z / d ln g(E, M) summed over the grid is
+//   sum_i exp(ln g(E, M) - beta_i E - A(i, M)) c(i, M).
+
+constexpr int GB = 8;  // beta values per thread in the column pass
+
+// One thread per (column M, block of GB betas); consecutive threads read
+// consecutive M of one energy row, so every row load is coalesced.
+__global__ void __launch_bounds__(TILE) k_grid_cols(Geo geo, const double* beta, int64_t nB, double* A,
+                                                     double* u1, double* u2) {
+    const int im = blockIdx.x * TILE + threadIdx.x;
+    const int64_t i0 = static_cast<int64_t>(blockIdx.y) * GB;
+    if (im >= geo.nM) return;
+    double b[GB], mx[GB], s0[GB], s1[GB];
+#pragma unroll
+    for (int k = 0; k < GB; ++k) {
+        b[k] = i0 + k < nB ? beta[i0 + k] : 0.0;
+        mx[k] = -INFINITY;
+        s0[k] = 0.0;
+        s1[k] = 0.0;
+    }
+    const double* col = geo.lng + im;
+    for (int ie = 0; ie < geo.nE; ++ie) {
+        const double l = col[static_cast<int64_t>(ie) * geo.nM];
+        if (l == -INFINITY) continue;
+        const double E = 4.0 * (geo.e0 + ie) - 2.0 * geo.N;
+#pragma unroll
+        for (int k = 0; k < GB; ++k) mx[k] = fmax(mx[k], l - b[k] * E);
+    }
+    if (mx[0] == -INFINITY) {  // an empty column is empty at every beta
+#pragma unroll
+        for (int k = 0; k < GB; ++k) {
+            if (i0 + k >= nB) break;
+            const int64_t o = (i0 + k) * geo.nM + im;
+            A[o] = -INFINITY;
+            if (u1) {
+                u1[o] = 0.0;
+                u2[o] = 0.0;
+            }
+        }
+        return;
+    }
+    for (int ie = 0; ie < geo.nE; ++ie) {
+        const double l = col[static_cast<int64_t>(ie) * geo.nM];
+        if (l == -INFINITY) continue;
+        const double E = 4.0 * (geo.e0 + ie) - 2.0 * geo.N;
+#pragma unroll
+        for (int k = 0; k < GB; ++k) {
+            const double w = exp((l - b[k] * E) - mx[k]);
+            s0[k] += w;
+            s1[k] += w * E;
+        }
+    }
+    if (u1) {
+        double mean[GB], s2[GB];
+#pragma unroll
+        for (int k = 0; k < GB; ++k) {
+            mean[k] = s1[k] / s0[k];
+            s2[k] = 0.0;
+        }
+        for (int ie = 0; ie < geo.nE; ++ie) {
+            const double l = col[static_cast<int64_t>(ie) * geo.nM];
+            if (l == -INFINITY) continue;
+            const double E = 4.0 * (geo.e0 + ie) - 2.0 * geo.N;
+#pragma unroll
+            for (int k = 0; k < GB; ++k) {
+                const double d = E - mean[k];
+                s2[k] += exp((l - b[k] * E) - mx[k]) * d * d;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < GB; ++k) {
+            if (i0 + k >= nB) break;
+            const int64_t o = (i0 + k) * geo.nM + im;
+            u1[o] = mean[k];
+            u2[o] = s2[k] / s0[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < GB; ++k) {
+        if (i0 + k >= nB) break;
+        A[(i0 + k) * geo.nM + im] = mx[k] + log(s0[k]);
+    }
+}
+
+// ln Z(i, j): one workgroup per (beta_i, 256 h values); the row A(i, .) is
+// staged through LDS in chunks and broadcast to the workgroup.
+__global__ void __launch_bounds__(TILE) k_grid_rows(const double* A, int N, int m0, int nM, const double* beta,
+                                                     const double* hf, int64_t nH, double* lnz) {
+    __shared__ double sa[TILE];
+    const int64_t i = blockIdx.x;
+    const int64_t j = static_cast<int64_t>(blockIdx.y) * TILE + threadIdx.x;
+    const bool on = j < nH;
+    const double bh = on ? beta[i] * hf[j] : 0.0;
+    const double* row = A + i * nM;
+    double mx = -INFINITY, sum = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int base = 0; base < nM; base += TILE) {
+            const int k = base + threadIdx.x;
+            __syncthreads();
+            sa[threadIdx.x] = k < nM ? row[k] : -INFINITY;
+            __syncthreads();
+            const int n = nM - base < TILE ? nM - base : TILE;
+            for (int q = 0; q < n; ++q) {
+                const double M = 2.0 * (m0 + base + q) - 1.0 * N;
+                const double x = sa[q] + bh * M;
+                if (pass == 0) mx = fmax(mx, x);
+                else if (sa[q] != -INFINITY) sum += exp(x - mx);
+            }
+        }
+    }
+    if (on) lnz[i * nH + j] = mx + log(sum);
+}
+
+// Per grid point (i, j), from the column statistics: with p_M = exp(A(i,M) +
+// beta_i h_j M - ln Z) and the conditional mean of U = -E + h M in column M,
+// ubar = -u1 + h M: <M>, <U>, then Var(U) = sum p (u2 + (ubar - <U>)^2),
+// Var(M), Cov(U, M) = sum p (ubar - <U>)(M - <M>) about those means.  Also
+// the per-point terms of the gradients: tb = g <U>, th = g beta <M>.
+__global__ void __launch_bounds__(TILE) k_grid_mom(const double* A, const double* u1, const double* u2, int N,
+                                                    int m0, int nM, const double* beta, const double* hf,
+                                                    int64_t nH, const double* lnz, const double* gout,
+                                                    double* mom, double* tb, double* th) {
+    __shared__ double sa[TILE], s1[TILE], s2[TILE];
+    const int64_t i = blockIdx.x;
+    const int64_t j = static_cast<int64_t>(blockIdx.y) * TILE + threadIdx.x;
+    const bool on = j < nH;
+    const double b = beta[i];
+    const double h = on ? hf[j] : 0.0;
+    const double bh = b * h;
+    const double z = on ? lnz[i * nH + j] : 0.0;
+    const int64_t r0 = i * nM;
+    double c0 = 0, cU = 0, cM = 0, mU = 0, mM = 0, vU = 0, vM = 0, cUM = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int base = 0; base < nM; base += TILE) {
+            const int k = base + threadIdx.x;
+            __syncthreads();
+            sa[threadIdx.x] = k < nM ? A[r0 + k] : -INFINITY;
+            s1[threadIdx.x] = k < nM ? u1[r0 + k] : 0.0;
+            s2[threadIdx.x] = k < nM ? u2[r0 + k] : 0.0;
+            __syncthreads();
+            const int n = nM - base < TILE ? nM - base : TILE;
+            for (int q = 0; q < n; ++q) {
+                if (sa[q] == -INFINITY) continue;
+                const double M = 2.0 * (m0 + base + q) - 1.0 * N;
+                const double p = exp(sa[q] + bh * M - z);
+                const double ub = -s1[q] + h * M;
+                if (pass == 0) {
+                    c0 += p;
+                    cU += p * ub;
+                    cM += p * M;
+                } else {
+                    const double du = ub - mU, dm = M - mM;
+                    vU += p * (s2[q] + du * du);
+                    vM += p * dm * dm;
+                    cUM += p * du * dm;
+                }
+            }
+        }
+        if (pass == 0) {
+            mU = cU / c0;
+            mM = cM / c0;
+        }
+    }
+    if (!on) return;
+    const int64_t o = i * nH + j;
+    if (mom) {
+        mom[5 * o + 0] = mM;
+        mom[5 * o + 1] = mU;
+        mom[5 * o + 2] = vU / c0;
+        mom[5 * o + 3] = vM / c0;
+        mom[5 * o + 4] = cUM / c0;
+    }
+    if (tb) {
+        const double go = gout ? gout[o] : 1.0;
+        tb[o] = go * mU;
+        th[o] = go * b * mM;
+    }
+}
+
+// grad_beta(i) = sum_j tb(i, j): one thread per beta_i, fixed order.
+__global__ void __launch_bounds__(TILE) k_grid_sum_rows(const double* tb, int64_t nB, int64_t nH, double* gbeta) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * TILE + threadIdx.x;
+    if (i >= nB) return;
+    double s = 0.0;
+    for (int64_t j = 0; j < nH; ++j) s += tb[i * nH + j];
+    gbeta[i] = s;
+}
+
+// grad_h(j) = sum_i th(i, j): one thread per h_j, coalesced over j.
+__global__ void __launch_bounds__(TILE) k_grid_sum_cols(const double* th, int64_t nB, int64_t nH, double* gh) {
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * TILE + threadIdx.x;
+    if (j >= nH) return;
+    double s = 0.0;
+    for (int64_t i = 0; i < nB; ++i) s += th[i * nH + j];
+    gh[j] = s;
+}
+
+// c(i, M) = sum_j grad_out(i, j) exp(A(i, M) + beta_i h_j M - ln Z(i, j)):
+// one thread per (i, M), the (h_j, ln Z(i, j), grad_out(i, j)) row staged in LDS.
+__global__ void __launch_bounds__(TILE) k_grid_colw(const double* A, int N, int m0, int nM, const double* beta,
+                                                     const double* hf, int64_t nH, const double* lnz,
+                                                     const double* gout, double* cw) {
+    __shared__ double sh[TILE], sz[TILE], sg[TILE];
+    const int64_t i = blockIdx.y;
+    const int im = blockIdx.x * TILE + threadIdx.x;
+    const bool on = im < nM;
+    const double a = on ? A[i * nM + im] : -INFINITY;
+    const double bM = beta[i] * (2.0 * (m0 + im) - 1.0 * N);
+    double acc = 0.0;
+    for (int64_t base = 0; base < nH; base += TILE) {
+        const int64_t k = base + threadIdx.x;
+        __syncthreads();
+        if (k < nH) {
+            sh[threadIdx.x] = hf[k];
+            sz[threadIdx.x] = lnz[i * nH + k];
+            sg[threadIdx.x] = gout ? gout[i * nH + k] : 1.0;
+        }
+        __syncthreads();
+        if (a == -INFINITY) continue;
+        const int n = static_cast<int>(nH - base < TILE ? nH - base : TILE);
+        for (int q = 0; q < n; ++q) acc += sg[q] * exp(a + bM * sh[q] - sz[q]);
+    }
+    if (on) cw[i * nM + im] = acc;
+}
+
+// grad ln g(E, M) = sum_i exp(ln g(E, M) - beta_i E - A(i, M)) c(i, M): one
+// thread per bin; A and c are read along M (coalesced), beta from LDS.
+__global__ void __launch_bounds__(TILE) k_grid_glng(Geo geo, const double* beta, int64_t nB, const double* A,
+                                                     const double* cw, double* glng) {
+    __shared__ double sb[TILE];
+    const int64_t nb = static_cast<int64_t>(geo.nE) * geo.nM;
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * TILE + threadIdx.x;
+    double E = 0, M = 0, l = -INFINITY;
+    int im = 0;
+    if (idx < nb) {
+        l = geo.lng[idx];
+        em_of(geo, idx, E, M);
+        im = static_cast<int>(idx % geo.nM);
+    }
+    double acc = 0.0;
+    for (int64_t base = 0; base < nB; base += TILE) {
+        const int64_t k = base + threadIdx.x;
+        __syncthreads();
+        if (k < nB) sb[threadIdx.x] = beta[k];
+        __syncthreads();
+        if (l == -INFINITY) continue;
+        const int n = static_cast<int>(nB - base < TILE ? nB - base : TILE);
+        for (int q = 0; q < n; ++q) {
+            const int64_t o = (base + q) * geo.nM + im;
+            acc += exp(l - sb[q] * E - A[o]) * cw[o];
+        }
+    }
+    if (idx < nb) glng[idx] = acc;
+}
+
 int nblk(int64_t n) { return static_cast<int>((n + TILE - 1) / TILE); }
 
 }  // namespace
@@ -203,6 +467,41 @@ hipError_t launch_lnz_grad_lng(const double* lng, int N, int e0, int nE, int m0,
     if (nb <= 0) return hipSuccess;
     Geo geo{lng, N, e0, nE, m0, nM};
     hipLaunchKernelGGL(k_lnz_glng, dim3(nblk(nb)), dim3(TILE), 0, st, geo, beta, h, G, lnz, grad_out, grad_lng);
+    return hipGetLastError();
+}
+
+hipError_t launch_lnz_grid_forward(const double* lng, int N, int e0, int nE, int m0, int nM, const double* beta,
+                                   int64_t nB, const double* h, int64_t nH, double* A, double* lnz, hipStream_t st) {
+    if (nB <= 0 || nH <= 0) return hipSuccess;
+    Geo geo{lng, N, e0, nE, m0, nM};
+    hipLaunchKernelGGL(k_grid_cols, dim3(nblk(nM), static_cast<unsigned>((nB + GB - 1) / GB)), dim3(TILE), 0, st,
+                       geo, beta, nB, A, static_cast<double*>(nullptr), static_cast<double*>(nullptr));
+    hipLaunchKernelGGL(k_grid_rows, dim3(static_cast<unsigned>(nB), nblk(nH)), dim3(TILE), 0, st, A, N, m0, nM, beta,
+                       h, nH, lnz);
+    return hipGetLastError();
+}
+
+hipError_t launch_lnz_grid_backward(const double* lng, int N, int e0, int nE, int m0, int nM, const double* beta,
+                                    int64_t nB, const double* h, int64_t nH, const double* lnz, const double* gout,
+                                    double* A, double* u1, double* u2, double* cw, double* tb, double* th,
+                                    double* gbeta, double* gh, double* glng, double* mom, hipStream_t st) {
+    if (nB <= 0 || nH <= 0) return hipSuccess;
+    Geo geo{lng, N, e0, nE, m0, nM};
+    hipLaunchKernelGGL(k_grid_cols, dim3(nblk(nM), static_cast<unsigned>((nB + GB - 1) / GB)), dim3(TILE), 0, st,
+                       geo, beta, nB, A, u1, u2);
+    if (mom || tb)
+        hipLaunchKernelGGL(k_grid_mom, dim3(static_cast<unsigned>(nB), nblk(nH)), dim3(TILE), 0, st, A, u1, u2, N,
+                           m0, nM, beta, h, nH, lnz, gout, mom, tb, th);
+    if (tb) {
+        hipLaunchKernelGGL(k_grid_sum_rows, dim3(nblk(nB)), dim3(TILE), 0, st, tb, nB, nH, gbeta);
+        hipLaunchKernelGGL(k_grid_sum_cols, dim3(nblk(nH)), dim3(TILE), 0, st, th, nB, nH, gh);
+    }
+    if (glng) {
+        hipLaunchKernelGGL(k_grid_colw, dim3(nblk(nM), static_cast<unsigned>(nB)), dim3(TILE), 0, st, A, N, m0, nM,
+                           beta, h, nH, lnz, gout, cw);
+        const int64_t nb = static_cast<int64_t>(nE) * nM;
+        hipLaunchKernelGGL(k_grid_glng, dim3(nblk(nb)), dim3(TILE), 0, st, geo, beta, nB, A, cw, glng);
+    }
     return hipGetLastError();
 }
 

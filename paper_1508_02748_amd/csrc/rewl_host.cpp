@@ -713,6 +713,61 @@ rewl_status rewl_lnz_backward(const double* lng, int32_t N, int32_t e0, int32_t 
     return REWL_OK;
 }
 
+// Tensor-product grids beta_i x h_j (factorised through the M columns).
+static rewl_status grid_check(const double* lng, int32_t N, int32_t e0, int32_t nE, int32_t m0, int32_t nM,
+                              const double* beta, int64_t nB, const double* h, int64_t nH) {
+    if (!lng || !beta || !h) return fail(REWL_EINVAL, "null pointer");
+    if (N < 1 || nE < 1 || nM < 1 || e0 < 0 || m0 < 0 || e0 + nE > N + 1 || m0 + nM > N + 1)
+        return fail(REWL_EINVAL, "bad reweighting geometry");
+    if (nB < 0 || nH < 0 || nB > 65535 || nH > 256LL * 65535) return fail(REWL_EINVAL, "bad grid size");
+    return REWL_OK;
+}
+
+static size_t grid_ws_bytes(int32_t nM, int64_t nB, int64_t nH) {
+    return (4 * static_cast<size_t>(nB) * static_cast<size_t>(nM) + 2 * static_cast<size_t>(nB) * nH) *
+           sizeof(double);
+}
+
+rewl_status rewl_lnz_grid_workspace_size(int32_t nM, int64_t nB, int64_t nH, size_t* bytes) {
+    if (!bytes || nM < 1 || nB < 0 || nH < 0) return fail(REWL_EINVAL, "bad arguments");
+    *bytes = grid_ws_bytes(nM, nB, nH);
+    return REWL_OK;
+}
+
+rewl_status rewl_lnz_grid_forward(const double* lng, int32_t N, int32_t e0, int32_t nE, int32_t m0, int32_t nM,
+                                  const double* beta, int64_t nB, const double* h, int64_t nH, void* workspace,
+                                  size_t workspace_bytes, double* lnz, void* hip_stream) {
+    rewl_status s = grid_check(lng, N, e0, nE, m0, nM, beta, nB, h, nH);
+    if (s != REWL_OK) return s;
+    if (!lnz || (!workspace && nB * nH > 0)) return fail(REWL_EINVAL, "null pointer");
+    if (workspace_bytes < grid_ws_bytes(nM, nB, nH)) return fail(REWL_EINVAL, "workspace too small");
+    hipError_t e = launch_lnz_grid_forward(lng, N, e0, nE, m0, nM, beta, nB, h, nH, static_cast<double*>(workspace),
+                                           lnz, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(REWL_EDEVICE, std::string("lnz grid forward: ") + hipGetErrorString(e));
+    return REWL_OK;
+}
+
+rewl_status rewl_lnz_grid_backward(const double* lng, int32_t N, int32_t e0, int32_t nE, int32_t m0, int32_t nM,
+                                   const double* beta, int64_t nB, const double* h, int64_t nH, const double* lnz,
+                                   const double* grad_out, void* workspace, size_t workspace_bytes,
+                                   double* grad_beta, double* grad_h, double* grad_lng, double* mom,
+                                   void* hip_stream) {
+    rewl_status s = grid_check(lng, N, e0, nE, m0, nM, beta, nB, h, nH);
+    if (s != REWL_OK) return s;
+    if (!lnz || (!workspace && nB * nH > 0)) return fail(REWL_EINVAL, "null pointer");
+    if ((grad_beta == nullptr) != (grad_h == nullptr)) return fail(REWL_EINVAL, "grad_beta and grad_h go together");
+    if (!grad_beta && !grad_lng && !mom) return fail(REWL_EINVAL, "nothing to compute");
+    if (workspace_bytes < grid_ws_bytes(nM, nB, nH)) return fail(REWL_EINVAL, "workspace too small");
+    const size_t cm = static_cast<size_t>(nB) * nM, ch = static_cast<size_t>(nB) * nH;
+    double* w = static_cast<double*>(workspace);
+    double *A = w, *u1 = w + cm, *u2 = w + 2 * cm, *cw = w + 3 * cm, *tb = w + 4 * cm, *th = tb + ch;
+    hipError_t e = launch_lnz_grid_backward(lng, N, e0, nE, m0, nM, beta, nB, h, nH, lnz, grad_out, A, u1, u2, cw,
+                                            grad_beta ? tb : nullptr, grad_beta ? th : nullptr, grad_beta, grad_h,
+                                            grad_lng, mom, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(REWL_EDEVICE, std::string("lnz grid backward: ") + hipGetErrorString(e));
+    return REWL_OK;
+}
+
 }  // extern "C"
 
 extern "C" rewl_status rewl_set_profile(rewl_plan* P, int32_t on) {

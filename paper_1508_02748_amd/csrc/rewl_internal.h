@@ -126,5 +126,13 @@ hipError_t launch_lnz_moments(const double* lng, int N, int e0, int nE, int m0, 
 hipError_t launch_lnz_grad_lng(const double* lng, int N, int e0, int nE, int m0, int nM,
                                const double* beta, const double* h, int64_t G, const double* lnz,
                                const double* grad_out, double* grad_lng, hipStream_t st);
+hipError_t launch_lnz_grid_forward(const double* lng, int N, int e0, int nE, int m0, int nM,
+                                   const double* beta, int64_t nB, const double* h, int64_t nH, double* A,
+                                   double* lnz, hipStream_t st);
+hipError_t launch_lnz_grid_backward(const double* lng, int N, int e0, int nE, int m0, int nM,
+                                    const double* beta, int64_t nB, const double* h, int64_t nH,
+                                    const double* lnz, const double* gout, double* A, double* u1, double* u2,
+                                    double* cw, double* tb, double* th, double* gbeta, double* gh,
+                                    double* glng, double* mom, hipStream_t st);
 
 }  // namespace rewl

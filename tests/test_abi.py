@@ -76,3 +76,24 @@ def test_mixed_interval_rejected():
     arr = (R._Problem * 2)(R.Problem(L=8, interval=100)._c(), R.Problem(L=8, interval=200)._c())
     h = C.c_void_p()
     assert L.rewl_plan_create(arr, 2, None, C.byref(h)) == R.REWL_EINVAL
+
+
+def test_grid_reweighting_validation_on_host():
+    R, L = _lib()
+    nb = C.c_size_t()
+    assert L.rewl_lnz_grid_workspace_size(1025, 1024, 256, C.byref(nb)) == 0
+    assert nb.value == (4 * 1024 * 1025 + 2 * 1024 * 256) * 8
+    assert L.rewl_lnz_grid_workspace_size(0, 4, 4, C.byref(nb)) == R.REWL_EINVAL
+    fake = C.c_void_p(256)   # never dereferenced: every call below fails validation first
+    # geometry outside the lattice, negative sizes, a workspace that is too small, no outputs
+    assert L.rewl_lnz_grid_forward(fake, 16, 0, 18, 0, 17, fake, 4, fake, 4, fake, 1 << 20, fake, None) \
+        == R.REWL_EINVAL
+    assert L.rewl_lnz_grid_forward(fake, 16, 0, 17, 0, 17, fake, -1, fake, 4, fake, 1 << 20, fake, None) \
+        == R.REWL_EINVAL
+    assert L.rewl_lnz_grid_forward(fake, 16, 0, 17, 0, 17, fake, 4, fake, 4, fake, 8, fake, None) \
+        == R.REWL_EINVAL
+    assert L.rewl_lnz_grid_backward(fake, 16, 0, 17, 0, 17, fake, 4, fake, 4, fake, None, fake, 1 << 20,
+                                    None, None, None, None, None) == R.REWL_EINVAL
+    assert L.rewl_lnz_grid_backward(fake, 16, 0, 17, 0, 17, fake, 4, fake, 4, fake, None, fake, 1 << 20,
+                                    fake, None, None, None, None) == R.REWL_EINVAL
+    assert L.rewl_last_error()

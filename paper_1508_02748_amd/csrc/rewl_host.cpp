@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/rewl.h"
+#include "rewl.h"
 #include "rewl_internal.h"
 
 using namespace rewl;

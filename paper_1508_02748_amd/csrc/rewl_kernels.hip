@@ -9,14 +9,20 @@
 //     During a sweep they live in LDS as lds[row * WG + lane] so that any mix
 //     of rows read by the 64 lanes hits 64 distinct consecutive words (no bank
 //     conflicts); in HBM they are packed per walker (row_words words per row).
-//   * ln g / H: one table per walker (single owner, no atomics), window rows
-//     e in [lo, hi] by all m in [0, N], 16-byte bins {ln g, H << 6 | stage}.
-//     The walker keeps the bin it currently occupies in registers and writes
-//     it back only when it leaves, so a trial costs one 16-byte gather of the
-//     proposed bin plus, on acceptance, one 16-byte store.
-//   * random numbers: Philox4x32-10 addressed by (seed; attempt block, walker,
-//     stream tag); one block serves two consecutive trials.
+//   * ln g: one int64 table per walker (single owner, no atomics) over the
+//     window rows e in [lo, hi] and all m in [0, N], in 4 x 4 tiles of
+//     (e, m) bins, one 128-byte line per tile, so the bins a walker can reach
+//     in the next few trials share a few lines.  H is not stored: a snapshot
+//     of ln g taken when the stage began gives H = (ln g - snapshot) >> (K - s).
+//     The walker keeps the bin it occupies in registers and writes it back only
+//     when it leaves, so a trial costs one 8-byte gather of the proposed bin
+//     plus, on acceptance, one 8-byte store.
+//   * random numbers: Philox4x32-10 addressed by (seed; trial block, walker,
+//     stream tag); one block serves two consecutive trials, and the next
+//     block's rounds run while each trial waits for its gather.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "rewl_internal.h"
 
@@ -231,17 +237,16 @@ __global__ void k_entry(DevState S, int64_t cap) {
 // precision estimate a of exp(x) (hardware exp2, relative error below 5e-6
 // for -23 < x < 0 including the rounding of x and u to float) decides unless
 // u lies within 1e-4 relative of a; only then is the double-precision
-// exp_neg evaluated.  Both branches give u < exp_neg(x) exactly.
-__device__ __forceinline__ bool accept_fast(int64_t delta, uint32_t u_word, int K) {
-    if (delta >= 0) return true;
-    if (delta <= -(static_cast<int64_t>(23) << K)) return false;
+// exp_neg evaluated.  Every path gives u < exp_neg(x) exactly.  The uniform
+// (u and its float rounding uf) is formed before the gathered ln g arrives,
+// and the filter has no branches: only the rare near-tie branches.
+__device__ __forceinline__ bool accept_pre(int64_t delta, double u, float uf, int K) {
     const double x = ldexp(static_cast<double>(delta), -K);
-    const double u = __dmul_rn(__dadd_rn(static_cast<double>(u_word), 0.5), 1.0 / 4294967296.0);
     const float a = __builtin_amdgcn_exp2f(static_cast<float>(x) * 1.44269504f);
-    const float uf = static_cast<float>(u);
-    if (uf < a * 0.9999f) return true;
-    if (uf > a * 1.0001f) return false;
-    return u < exp_neg(x);
+    bool acc = delta >= 0 || uf < a * 0.9999f;
+    const bool rej = delta <= -(static_cast<int64_t>(23) << K) || uf > a * 1.0001f;
+    if (!acc && !rej) acc = u < exp_neg(x);
+    return acc;
 }
 
 // First and second halves of a Philox4x32-10 evaluation, so that the next
@@ -259,19 +264,32 @@ template <int NR>
 __device__ __forceinline__ void philox_rounds(PhiloxRun& q) {
 #pragma unroll
     for (int round = 0; round < NR; ++round) {
-        const uint32_t a_lo = 0xD2511F53u * q.c0;
-        const uint32_t a_hi = __umulhi(0xD2511F53u, q.c0);
-        const uint32_t b_lo = 0xCD9E8D57u * q.c2;
-        const uint32_t b_hi = __umulhi(0xCD9E8D57u, q.c2);
-        const uint32_t n0 = b_hi ^ q.c1 ^ q.k0;
-        const uint32_t n2 = a_hi ^ q.c3 ^ q.k1;
+        // one 32x32 -> 64 multiply per product (low and high words together)
+        const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * q.c0;
+        const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * q.c2;
+        const uint32_t n0 = static_cast<uint32_t>(pb >> 32) ^ q.c1 ^ q.k0;
+        const uint32_t n2 = static_cast<uint32_t>(pa >> 32) ^ q.c3 ^ q.k1;
         q.c0 = n0;
-        q.c1 = b_lo;
+        q.c1 = static_cast<uint32_t>(pb);
         q.c2 = n2;
-        q.c3 = a_lo;
+        q.c3 = static_cast<uint32_t>(pa);
         q.k0 += 0x9E3779B9u;
         q.k1 += 0xBB67AE85u;
     }
+}
+
+struct NoRounds {};
+
+// Pins the Philox state and the gathered ln g in registers at this point of
+// the trial: the rounds computed before it overlap the table gather issued
+// before them (instead of being moved after the acceptance branch), and the
+// gather is waited for here on every path, not only inside the branch.
+__device__ __forceinline__ void pin(PhiloxRun& q, int64_t& v, float& f) {
+    asm volatile("" : "+v"(q.c0), "+v"(q.c1), "+v"(q.c2), "+v"(q.c3), "+v"(v), "+v"(f) : : "memory");
+}
+
+__device__ __forceinline__ void pin(NoRounds&, int64_t& v, float& f) {
+    asm volatile("" : "+v"(v), "+v"(f) : : "memory");
 }
 
 // n_trials Wang-Landau trials (Eq. 1) for walker g (lane `lane` of a
@@ -293,6 +311,7 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
     const uint64_t seed = P.seed;
     const uint32_t gid = static_cast<uint32_t>(d.gid);
     int64_t* tab = S.lng + d.table_off;
+    const int wsh = __builtin_ctz(static_cast<unsigned>(WG));  // WG is 64, 128 or 256
 
     const uint32_t* gsp = S.spins + d.spin_off;
     for (int r = 0; r < L; ++r) {
@@ -309,17 +328,18 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
     uint32_t cur = tile_index(e - lo, m, ntm);
     int64_t lng_cur = tab[cur];
 
-    // One trial with the words (sw, uw) of its Philox block.
-    auto trial = [&](uint32_t sw, uint32_t uw) {
+    // One trial with the words (sw, uw) of its Philox block; `q` (a PhiloxRun)
+    // advances the next block by five rounds while the gather is in flight.
+    auto trial = [&](uint32_t sw, uint32_t uw, auto& q) {
         int r, c;
         site_rc(sw, L, r, c);
         const int ru = r == 0 ? L - 1 : r - 1;
         const int rd = r == L - 1 ? 0 : r + 1;
         const int cl = c == 0 ? L - 1 : c - 1;
         const int cr = c == L - 1 ? 0 : c + 1;
-        const RowT row = lds[r * WG + lane];
-        const RowT rowu = lds[ru * WG + lane];
-        const RowT rowd = lds[rd * WG + lane];
+        const RowT row = lds[(r << wsh) + lane];
+        const RowT rowu = lds[(ru << wsh) + lane];
+        const RowT rowd = lds[(rd << wsh) + lane];
         const uint32_t bc = static_cast<uint32_t>(row >> c) & 1u;
         // number of the four neighbours anti-aligned with the site
         const uint32_t k = ((static_cast<uint32_t>(row >> cl) & 1u) ^ bc) +
@@ -331,10 +351,14 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
         const bool in = e2 >= lo && e2 <= hi;
         // gather unconditionally (a bin of the current row when out of the window)
         const uint32_t idx2 = tile_index((in ? e2 : e) - lo, m2, ntm);
-        const int64_t lng2 = tab[idx2];
-        if (in && accept_fast(lng_cur - lng2, uw, K)) {
+        int64_t lng2 = tab[idx2];
+        const double u = __dmul_rn(__dadd_rn(static_cast<double>(uw), 0.5), 1.0 / 4294967296.0);
+        float uf = static_cast<float>(u);
+        if constexpr (!std::is_same_v<std::decay_t<decltype(q)>, NoRounds>) philox_rounds<5>(q);
+        pin(q, lng2, uf);
+        if (in && accept_pre(lng_cur - lng2, u, uf, K)) {
             tab[cur] = lng_cur;
-            lds[r * WG + lane] = row ^ (static_cast<RowT>(1) << c);
+            lds[(r << wsh) + lane] = row ^ (static_cast<RowT>(1) << c);
             e = e2;
             m = m2;
             cur = idx2;
@@ -347,10 +371,11 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
 
     int64_t i = 0;
     Words4 blk = {0, 0, 0, 0};
+    NoRounds none;
     if (n_trials > 0 && (t & 1)) {  // odd start: second half of the current block
         const uint64_t b = static_cast<uint64_t>(t) >> 1;
         blk = philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid, TAG_WL << 24);
-        trial(blk.z, blk.w);
+        trial(blk.z, blk.w, none);
         ++i;
     }
     if (i + 2 <= n_trials) {
@@ -359,18 +384,16 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
     }
     for (; i + 2 <= n_trials; i += 2) {
         // t is even here; blk is block t/2; the next block is computed in two
-        // halves interleaved with this pair of trials
+        // halves, each under the table gather of one of this pair of trials
         PhiloxRun q = philox_start(seed, (static_cast<uint64_t>(t) >> 1) + 1, gid);
-        philox_rounds<5>(q);
-        trial(blk.x, blk.y);
-        philox_rounds<5>(q);
-        trial(blk.z, blk.w);
+        trial(blk.x, blk.y, q);
+        trial(blk.z, blk.w, q);
         blk = {q.c0, q.c1, q.c2, q.c3};
     }
     if (i < n_trials) {  // one trial left, t even: first half of block t/2
         const uint64_t b = static_cast<uint64_t>(t) >> 1;
         blk = philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid, TAG_WL << 24);
-        trial(blk.x, blk.y);
+        trial(blk.x, blk.y, none);
     }
     tab[cur] = lng_cur;
     S.e[g] = e;
@@ -408,11 +431,15 @@ __global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int6
 }
 
 // ------------------------------------------------------------------ flatness
-// One wavefront per walker scans its table 64 bins at a time, starting where
-// the previous scan failed: the walker is flat iff every visited bin (ln g >
-// 0) has flat_den * H * n_seen >= flat_num * sum H, with H = (ln g -
-// snapshot) >> (K - s) and sum H = trials made in this stage.  The first
-// failing chunk ends the scan; the latch is set only after a full pass.
+// One wavefront per walker scans its table in chunks of 64 bins, four chunks
+// (eight loads per lane) in flight at a time, starting where the previous
+// scan failed: the walker is flat iff every visited bin (ln g > 0) has
+// flat_den * H * n_seen >= flat_num * sum H, with H = (ln g - snapshot) >>
+// (K - s) and sum H = trials made in this stage.  The first failing chunk in
+// scan order ends the scan and is where the next one starts; the latch is
+// set only after a full pass, so the result does not depend on the order.
+constexpr int FLAT_GROUP = 4;
+
 __global__ void __launch_bounds__(256) k_flat(DevState S) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t g = static_cast<int64_t>(blockIdx.x) * 4 + wave;
@@ -432,21 +459,30 @@ __global__ void __launch_bounds__(256) k_flat(DevState S) {
     int64_t c0 = S.scan[g];
     if (c0 >= nch) c0 = 0;
     const unsigned __int128 rhs = static_cast<unsigned __int128>(static_cast<uint64_t>(P.flat_num)) * sum;
-    for (int64_t k = 0; k < nch; ++k) {
-        int64_t c = c0 + k;
-        if (c >= nch) c -= nch;
-        const int64_t i = c * 64 + lane;
-        int fail = 0;
-        if (i < nb) {
-            const int64_t l = tab[i];
-            if (l != 0) {
-                const uint64_t H = static_cast<uint64_t>(l - snp[i]) >> sh;
+    for (int64_t k = 0; k < nch; k += FLAT_GROUP) {
+        int64_t c[FLAT_GROUP], l[FLAT_GROUP], sn[FLAT_GROUP];
+        bool on[FLAT_GROUP];
+#pragma unroll
+        for (int j = 0; j < FLAT_GROUP; ++j) {
+            int64_t cj = c0 + k + j;
+            if (cj >= nch) cj -= nch;
+            c[j] = cj;
+            const int64_t i = cj * 64 + lane;
+            on[j] = k + j < nch && i < nb;
+            l[j] = on[j] ? tab[i] : 0;
+            sn[j] = on[j] ? snp[i] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < FLAT_GROUP; ++j) {
+            int fail = 0;
+            if (l[j] != 0) {
+                const uint64_t H = static_cast<uint64_t>(l[j] - sn[j]) >> sh;
                 fail = static_cast<unsigned __int128>(static_cast<uint64_t>(P.flat_den)) * H * n < rhs;
             }
-        }
-        if (__any(fail)) {
-            if (lane == 0) S.scan[g] = static_cast<uint32_t>(c);
-            return;
+            if (__any(fail)) {
+                if (lane == 0) S.scan[g] = static_cast<uint32_t>(c[j]);
+                return;
+            }
         }
     }
     if (lane == 0) S.flag[g] = 1;

@@ -20,6 +20,15 @@ Steps, in the paper's order:
 5. Normalisation: either sum_{E,M} g = 2^N or the ground-state count
    g(E = -2N) = 2.
 
+Error bars (Sec. 2, last paragraph: several walkers per window make error
+bars possible): for each bin, the standard error of the window average over
+the walkers that visited it, sqrt(sum_a (x_a - mean)^2 / (n (n - 1))) with
+x_a the aligned values; this is the jackknife (leave-one-walker-out) error of
+that mean with the alignment constants held fixed.  NaN where fewer than two
+walkers visited the bin.  The joint table's error in row e is the error of
+the window that supplies row e in Eq. (4) (the matching constants are not
+counted).
+
 Tables are float64 arrays (N+1, N+1) indexed by (e, m) with -inf where a bin
 was never visited; e = (E + 2N)/4, m = (M + N)/2.
 """
@@ -37,11 +46,12 @@ def _lse(a, axis=None):
     return np.squeeze(out, axis=axis) if axis is not None else float(out.reshape(()))
 
 
-def window_average(frags, K):
+def window_average(frags, K, with_err=False):
     """Step 1: combine the int64 fixed-point tables of one window's walkers.
 
     frags: list of int64 arrays (n_E, N+1) (units 2^-K; 0 = never visited).
-    Returns float64 (n_E, N+1) with -inf on bins no walker visited."""
+    Returns float64 (n_E, N+1) with -inf on bins no walker visited, and with
+    ``with_err`` also the standard error of that average over the walkers."""
     vals = [f.astype(np.float64) * 2.0 ** -K for f in frags]
     seen = [f > 0 for f in frags]
     common = np.logical_and.reduce(seen)
@@ -56,7 +66,15 @@ def window_average(frags, K):
     out = np.full(vals[0].shape, -np.inf)
     nz = cnt > 0
     out[nz] = num[nz] / cnt[nz]
-    return out
+    if not with_err:
+        return out
+    ss = np.zeros_like(out)
+    for v, s in zip(shifted, seen):
+        ss[s] += (v[s] - out[s]) ** 2
+    err = np.full(out.shape, np.nan)
+    two = cnt > 1
+    err[two] = np.sqrt(ss[two] / (cnt[two] * (cnt[two] - 1)))
+    return out, err
 
 
 def marginal(lng_joint):
@@ -72,12 +90,13 @@ def beta_central(lnge):
     return b
 
 
-def merge(pieces, N, norm="ground"):
+def merge(pieces, N, norm="ground", errs=None):
     """Join window pieces into the full joint DOS (Eq. 4).
 
     pieces: list (ordered by energy) of (lo, hi, lng) with lng float64 of shape
     (hi - lo + 1, N + 1) (-inf = unvisited), already averaged over walkers.
-    Returns (lng_joint (N+1, N+1), lng_marginal (N+1,), e_mat list)."""
+    Returns (lng_joint (N+1, N+1), lng_marginal (N+1,), e_mat list), and with
+    ``errs`` (one error table per piece) also the joint error table."""
     full = []
     for lo, hi, t in pieces:
         f = np.full((N + 1, N + 1), -np.inf)
@@ -107,7 +126,15 @@ def merge(pieces, N, norm="ground"):
         prev_mat = e_mat
         e_mats.append(e_mat)
     joint = normalise(joint, N, norm)
-    return joint, marginal(joint), e_mats
+    if errs is None:
+        return joint, marginal(joint), e_mats
+    jerr = np.full((N + 1, N + 1), np.nan)
+    bounds = [0] + e_mats + [N + 1]
+    for j, (lo, hi, _) in enumerate(pieces):
+        a, b = max(bounds[j], lo), min(bounds[j + 1], hi + 1)
+        if a < b:
+            jerr[a:b] = errs[j][a - lo:b - lo]
+    return joint, marginal(joint), e_mats, jerr
 
 
 def normalise(joint, N, norm="ground"):
@@ -124,11 +151,13 @@ def relative_error(lnge_sim, lnge_exact):
     return np.abs(lnge_sim[ok] - lnge_exact[ok]) / lnge_exact[ok]
 
 
-def merge_oracle_run(orc, norm="ground"):
-    """Merge all walkers of an OracleREWL simulation into (joint, marginal, e_mats)."""
-    pieces = []
+def merge_oracle_run(orc, norm="ground", with_err=False):
+    """Merge all walkers of an OracleREWL simulation into (joint, marginal, e_mats[, joint_err])."""
+    pieces, errs = [], []
     for w in range(orc.n_windows):
         frags = [orc.walker(w * orc.W + a)["lng"] for a in range(orc.W)]
         lo, hi = orc.window(w)
-        pieces.append((lo, hi, window_average(frags, orc.K)))
-    return merge(pieces, orc.N, norm)
+        avg, err = window_average(frags, orc.K, with_err=True)
+        pieces.append((lo, hi, avg))
+        errs.append(err)
+    return merge(pieces, orc.N, norm, errs if with_err else None)

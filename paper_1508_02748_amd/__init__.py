@@ -87,7 +87,7 @@ def lib():
             "rewl_save_size": ([P, C.POINTER(C.c_size_t)], C.c_int),
             "rewl_save": ([P, P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
             "rewl_load": ([P, P, C.c_size_t], C.c_int),
-            "rewl_merge_lng": ([P, C.c_int32, C.c_int32, P, C.c_size_t, P, P, P], C.c_int),
+            "rewl_merge_lng": ([P, C.c_int32, C.c_int32, P, C.c_size_t, P, P, P, P], C.c_int),
             "rewl_last_error": ([], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -227,8 +227,9 @@ class Plan:
         _check(lib().rewl_sweep_times(self._h, buf.ctypes.data, cap, C.byref(n)))
         return buf[:min(cap, n.value)].astype(np.float64)
 
-    def merge(self, prob=0, norm="ground"):
-        """Joint ln g(E, M) (device, float64, (N+1) x (N+1)), marginal ln g(E), E_mat list."""
+    def merge(self, prob=0, norm="ground", with_err=False):
+        """Joint ln g(E, M) (device, float64, (N+1) x (N+1)), marginal ln g(E), E_mat list
+        [, error bars of the joint table (device, NaN below two walkers)]."""
         import torch
         p = self.problems[prob]
         nb = C.c_size_t()
@@ -237,11 +238,13 @@ class Plan:
         joint = torch.empty((p.N + 1, p.N + 1), dtype=torch.float64, device=self.device)
         marg = torch.empty(p.N + 1, dtype=torch.float64, device=self.device)
         emat = torch.zeros(max(1, p.n_windows - 1), dtype=torch.int32, device=self.device)
+        err = torch.empty_like(joint) if with_err else None
         torch.cuda.current_stream(self.device).synchronize()
         _check(lib().rewl_merge_lng(self._h, prob, {"ground": 0, "sum": 1}[norm], C.c_void_p(ws.data_ptr()),
                                     nb.value, C.c_void_p(joint.data_ptr()), C.c_void_p(marg.data_ptr()),
-                                    C.c_void_p(emat.data_ptr())))
-        return joint, marg, [int(x) for x in emat.cpu()[:p.n_windows - 1]]
+                                    C.c_void_p(emat.data_ptr()), _ptr(err)))
+        em = [int(x) for x in emat.cpu()[:p.n_windows - 1]]
+        return (joint, marg, em, err) if with_err else (joint, marg, em)
 
     def window(self, prob, w):
         lo, hi = C.c_int32(), C.c_int32()

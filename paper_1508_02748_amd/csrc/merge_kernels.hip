@@ -4,7 +4,10 @@
 //   k_merge_window   one workgroup per window: each walker is aligned on its
 //                    mean over the bins every walker of the window has visited
 //                    (exact int128 sums), then ln g is averaged over the
-//                    walkers that visited each bin.
+//                    walkers that visited each bin, with the standard error of
+//                    that average over the walkers (the leave-one-walker-out
+//                    jackknife error with the alignment held fixed; NaN below
+//                    two walkers) stored after the window's averages.
 //   k_merge_marginal one wavefront per (window, energy row): Eq. (3),
 //                    ln g(E) = log sum_M g(E, M).
 //   k_merge_join     one thread: for each neighbouring pair of windows the
@@ -88,7 +91,17 @@ __global__ void __launch_bounds__(256) k_merge_window(DevState S, MergeGeo G) {
                 ++cnt;
             }
         }
-        avg[i] = cnt > 0 ? num / cnt : -INFINITY;
+        const double mean = cnt > 0 ? num / cnt : -INFINITY;
+        avg[i] = mean;
+        double ss = 0.0;
+        for (int a = 0; a < W; ++a) {
+            const int64_t l = lng_at(S, S.wd[g0 + a], er, m);
+            if (l > 0) {
+                const double dv = (static_cast<double>(l) * unit - shift[a]) - mean;
+                ss += dv * dv;
+            }
+        }
+        avg[nb + i] = cnt > 1 ? sqrt(ss / (static_cast<double>(cnt) * (cnt - 1))) : NAN;
     }
 }
 
@@ -163,7 +176,7 @@ __global__ void k_merge_join(DevState S, MergeGeo G, int32_t* e_mat_out) {
     }
 }
 
-__global__ void __launch_bounds__(256) k_merge_fill(DevState S, MergeGeo G, double* out) {
+__global__ void __launch_bounds__(256) k_merge_fill(DevState S, MergeGeo G, double* out, double* err) {
     const PDesc P = S.pd[G.prob];
     const int N = P.N, nM = N + 1;
     const int64_t total = static_cast<int64_t>(nM) * nM;
@@ -174,9 +187,14 @@ __global__ void __launch_bounds__(256) k_merge_fill(DevState S, MergeGeo G, doub
     for (int k = 1; k < P.nwin; ++k)
         if (e >= G.emat[k]) j = k;
     const WDesc d = S.wd[P.walker_off + j * P.W];
-    double v = -INFINITY;
-    if (e >= d.lo && e <= d.hi) v = G.ws[G.off_avg[j] + static_cast<int64_t>(e - d.lo) * nM + m] + G.ws[G.off_pshift + j];
+    double v = -INFINITY, ev = NAN;
+    if (e >= d.lo && e <= d.hi) {
+        const int64_t k = G.off_avg[j] + static_cast<int64_t>(e - d.lo) * nM + m;
+        v = G.ws[k] + G.ws[G.off_pshift + j];
+        ev = G.ws[k + static_cast<int64_t>(d.hi - d.lo + 1) * nM];
+    }
     out[i] = v;
+    if (err) err[i] = ev;
 }
 
 __global__ void __launch_bounds__(64) k_merge_rows(int N, const double* joint, double* rows) {
@@ -207,13 +225,13 @@ __global__ void __launch_bounds__(256) k_merge_apply(int N, double* joint, doubl
 }  // namespace
 
 hipError_t launch_merge(const DevState& S, const MergeGeo& G, int N, int nwin, int max_nE, int norm, double* lng_out,
-                        double* lnge_out, int32_t* e_mat_out, hipStream_t st) {
+                        double* lnge_out, int32_t* e_mat_out, double* err_out, hipStream_t st) {
     hipLaunchKernelGGL(k_merge_window, dim3(nwin), dim3(256), 0, st, S, G);
     hipLaunchKernelGGL(k_merge_marginal, dim3(max_nE, nwin), dim3(64), 0, st, S, G);
     hipLaunchKernelGGL(k_merge_join, dim3(1), dim3(64), 0, st, S, G, e_mat_out);
     const int64_t total = static_cast<int64_t>(N + 1) * (N + 1);
     const int blocks = static_cast<int>((total + 255) / 256);
-    hipLaunchKernelGGL(k_merge_fill, dim3(blocks), dim3(256), 0, st, S, G, lng_out);
+    hipLaunchKernelGGL(k_merge_fill, dim3(blocks), dim3(256), 0, st, S, G, lng_out, err_out);
     hipLaunchKernelGGL(k_merge_rows, dim3(N + 1), dim3(64), 0, st, N, lng_out, lnge_out);
     hipLaunchKernelGGL(k_merge_norm, dim3(1), dim3(64), 0, st, N, norm, lnge_out, G.ws + G.off_cst);
     hipLaunchKernelGGL(k_merge_apply, dim3(blocks), dim3(256), 0, st, N, lng_out, lnge_out, G.ws + G.off_cst);

@@ -821,7 +821,7 @@ rewl_status merge_layout(const rewl_plan* P, int32_t prob, char* base, MergeLayo
         const int nE = P->hi[prob][w] - P->lo[prob][w] + 1;
         max_nE = std::max(max_nE, nE);
         G.off_avg[w] = o;
-        o += static_cast<int64_t>(nE) * nM;
+        o += 2 * static_cast<int64_t>(nE) * nM;  // averages, then their standard errors
     }
     const size_t dbl_bytes = align_up(static_cast<size_t>(o) * sizeof(double), 256);
     // integer region (256-byte aligned): 4 flags (16 bytes, cleared with one
@@ -847,7 +847,7 @@ extern "C" rewl_status rewl_merge_workspace_size(const rewl_plan* P, int32_t pro
 }
 
 extern "C" rewl_status rewl_merge_lng(rewl_plan* P, int32_t prob, int32_t norm, void* workspace, size_t ws_bytes,
-                                      double* lng_out, double* lnge_out, int32_t* e_mat_out) {
+                                      double* lng_out, double* lnge_out, int32_t* e_mat_out, double* lng_err_out) {
     rewl_status s = usable(P);
     if (s != REWL_OK) return s;
     if (!P->initialised) return fail(REWL_ESTATE, "rewl_init has not run");
@@ -858,7 +858,8 @@ extern "C" rewl_status rewl_merge_lng(rewl_plan* P, int32_t prob, int32_t norm, 
     if (ws_bytes < ml.bytes) return fail(REWL_EINVAL, "workspace too small");
     const PDesc& q = P->pd[prob];
     HIPCHK(P, launch_zero(ml.G.flags, 16, P->stream), "merge flag clear");
-    HIPCHK(P, launch_merge(P->S, ml.G, q.N, q.nwin, ml.max_nE, norm, lng_out, lnge_out, e_mat_out, P->stream),
+    HIPCHK(P, launch_merge(P->S, ml.G, q.N, q.nwin, ml.max_nE, norm, lng_out, lnge_out, e_mat_out, lng_err_out,
+                           P->stream),
            "merge launch");
     int32_t flags[4];
     HIPCHK(P, hipMemcpyAsync(flags, ml.G.flags, 16, hipMemcpyDeviceToHost, P->stream), "merge flag read");

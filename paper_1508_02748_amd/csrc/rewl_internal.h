@@ -95,7 +95,8 @@ struct MergeGeo {
     int64_t off_mg;      // N + 1: marginal of the pieces joined so far
     int64_t off_pshift;  // n_windows additive constants of the pieces
     int64_t off_cst;     // normalisation constant
-    int64_t off_avg[MERGE_MAX_WINDOWS];  // window-averaged tables, (hi-lo+1) x (N+1)
+    int64_t off_avg[MERGE_MAX_WINDOWS];  // window-averaged tables, (hi-lo+1) x (N+1), each
+                                         // followed by its standard-error table
     int32_t* emat;       // n_windows matching points (emat[0] = 0)
     int32_t* flags;      // [0] != 0: no common bin (1) or no matching point (2)
 };
@@ -113,7 +114,7 @@ hipError_t launch_snapshot(const DevState& S, hipStream_t st);
 hipError_t launch_exchange(const DevState& S, hipStream_t st);
 
 hipError_t launch_merge(const DevState& S, const MergeGeo& G, int N, int nwin, int max_nE, int norm,
-                        double* lng_out, double* lnge_out, int32_t* e_mat_out, hipStream_t st);
+                        double* lng_out, double* lnge_out, int32_t* e_mat_out, double* err_out, hipStream_t st);
 
 // Reweighting.
 hipError_t launch_lnz_forward(const double* lng, int N, int e0, int nE, int m0, int nM,

@@ -15,7 +15,7 @@ import os
 from . import FORM_BATCHED, Tuning
 
 WG_CANDIDATES = (64, 128, 256)
-GRID_CANDIDATES = (0, 2, 3, 4, 5, 6, 8)
+GRID_CANDIDATES = (2, 3, 4, 5, 6, 8)
 
 
 def _cache_path():

@@ -37,10 +37,14 @@ def _pair(R, p, n_intervals):
 
 
 def _check(plan, o, norm):
-    j, g, em = plan.merge(0, norm)
-    j, g = j.cpu().numpy(), g.cpu().numpy()
-    rj, rg, rem = MG.merge_oracle_run(o, norm)
+    j, g, em, err = plan.merge(0, norm, with_err=True)
+    j, g, err = j.cpu().numpy(), g.cpu().numpy(), err.cpu().numpy()
+    rj, rg, rem, rerr = MG.merge_oracle_run(o, norm, with_err=True)
     assert em == rem, (em, rem)
+    # error bars: NaN exactly where fewer than two walkers visited, else equal to ~1e-12
+    assert (np.isnan(err) == np.isnan(rerr)).all()
+    ok = ~np.isnan(rerr)
+    assert np.max(np.abs(err[ok] - rerr[ok]), initial=0.0) < 1e-9
     fin = np.isfinite(rj)
     assert (np.isfinite(j) == fin).all()
     assert np.max(np.abs(j[fin] - rj[fin])) < 1e-9

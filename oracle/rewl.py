@@ -4,7 +4,9 @@ The oracle runs one REWL simulation per ``OracleREWL`` object, exactly as the
 paper describes it (Sec. 2): independent WL walkers per overlapping energy
 window, each with its own ln g(E,M) and H(E,M); flatness checks; a global
 f -> sqrt(f) refinement once every walker is flat; configuration exchange
-between adjacent windows with Eq. (2).  Tables are returned as numpy arrays of
+between adjacent windows with Eq. (2).  With ``sync=1`` each window refines
+alone once its own walkers are flat, averaging their ln g first (a common
+REWL form the paper cites; not the paper's own runs).  Tables are returned as numpy arrays of
 shape (hi - lo + 1, N + 1) indexed by (e - lo, m), with e = (E + 2N)/4 and
 m = (M + N)/2.
 """
@@ -72,6 +74,11 @@ def lib():
         L.or_set_walker.restype = None
         L.or_set_stage.argtypes = [C.c_void_p, C.c_int]
         L.or_set_stage.restype = None
+        L.or_set_sync.argtypes = [C.c_void_p, C.c_int]
+        L.or_set_sync.restype = C.c_int
+        L.or_window_state.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int)]
+        L.or_window_state.restype = None
         _lib = L
     return _lib
 
@@ -115,7 +122,7 @@ class OracleREWL:
     """One 2D-REWL simulation (all windows and walkers of one problem)."""
 
     def __init__(self, L, n_windows=1, overlap=(3, 4), walkers_per_window=1,
-                 k_final=16, flat=(4, 5), interval=10_000, seed=0, init=0):
+                 k_final=16, flat=(4, 5), interval=10_000, seed=0, init=0, sync=0):
         self.L, self.N = L, L * L
         self.n_windows, self.W = n_windows, walkers_per_window
         self.K, self.X, self.seed = k_final, interval, seed
@@ -126,6 +133,9 @@ class OracleREWL:
         if not h:
             raise ValueError("invalid REWL problem")
         self._h = h
+        self.sync = sync
+        if lib().or_set_sync(h, sync) != 0:
+            raise ValueError("sync must be 0 (all windows together) or 1 (per window)")
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -168,6 +178,12 @@ class OracleREWL:
         lo, hi = C.c_int(), C.c_int()
         lib().or_window_of(self._h, w, C.byref(lo), C.byref(hi))
         return lo.value, hi.value
+
+    def window_state(self, w):
+        """(stage, done) of window w."""
+        s, d = C.c_int(), C.c_int()
+        lib().or_window_state(self._h, w, C.byref(s), C.byref(d))
+        return s.value, bool(d.value)
 
     def walker(self, g, tables=True):
         """State of walker g = w * W + a as a dict of numpy arrays / ints."""

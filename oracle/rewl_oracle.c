@@ -169,9 +169,12 @@ typedef struct {
     int64_t **lng;     /* [nwalk][(hi-lo+1)(N+1)]  ln g in units 2^-K */
     uint64_t **H;      /* same shape */
     uint8_t *flag;     /* flat in the current stage (latched) */
-    int s;             /* stage: ln f = 2^-s */
+    int s;             /* stage: ln f = 2^-s (the lowest window stage) */
     int done;
     int64_t r;         /* interval boundaries passed */
+    int sync;          /* 0: all windows refine together; 1: each window alone */
+    int *sw;           /* stage of each window */
+    uint8_t *wdone;    /* window has finished its last stage */
 } or_rewl;
 
 static int win_of(const or_rewl *P, int g) { return g / P->W; }
@@ -190,6 +193,7 @@ OR_EXPORT void or_destroy(or_rewl *P) {
         for (int g = 0; g < P->nwalk; ++g) free(P->H[g]);
     free(P->lng); free(P->H); free(P->lo); free(P->hi); free(P->spin);
     free(P->e); free(P->m); free(P->t); free(P->te); free(P->flag);
+    free(P->sw); free(P->wdone);
     free(P);
 }
 
@@ -217,8 +221,10 @@ OR_EXPORT or_rewl *or_create(int L, int n_win, int ovl_num, int ovl_den, int W,
     P->flag = calloc(P->nwalk, 1);
     P->lng = calloc(P->nwalk, sizeof(int64_t *));
     P->H = calloc(P->nwalk, sizeof(uint64_t *));
+    P->sw = calloc(n_win, sizeof(int));
+    P->wdone = calloc(n_win, 1);
     if (!P->lo || !P->hi || !P->spin || !P->e || !P->m || !P->t || !P->te ||
-        !P->flag || !P->lng || !P->H) {
+        !P->flag || !P->lng || !P->H || !P->sw || !P->wdone) {
         or_destroy(P);
         return NULL;
     }
@@ -352,7 +358,7 @@ static void wl_attempt(or_rewl *P, int g) {
         P->m[g] = m = m2;
     }
     int64_t bi = bin_index(P, w, e, m);
-    P->lng[g][bi] += (int64_t)1 << (P->K - P->s);
+    P->lng[g][bi] += (int64_t)1 << (P->K - P->sw[w]);
     P->H[g][bi] += 1;
     P->t[g] += 1;
 }
@@ -362,8 +368,10 @@ static void wl_attempt(or_rewl *P, int g) {
 OR_EXPORT void or_sweep(or_rewl *P, int64_t n) {
     if (P->done) return;
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int g = 0; g < P->nwalk; ++g)
+    for (int g = 0; g < P->nwalk; ++g) {
+        if (P->wdone[win_of(P, g)]) continue;  /* a finished window stops */
         for (int64_t i = 0; i < n; ++i) wl_attempt(P, g);
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -424,6 +432,7 @@ OR_EXPORT int64_t or_exchange(or_rewl *P, int64_t r) {
         for (int a = 0; a < W; ++a) {
             int A = w * W + a, B = (w + 1) * W + pi[a];
             int eA = P->e[A], mA = P->m[A], eB = P->e[B], mB = P->m[B];
+            if (P->wdone[w] || P->wdone[w + 1]) continue;
             if (eA < P->lo[w + 1] || eA > P->hi[w + 1]) continue;
             if (eB < P->lo[w] || eB > P->hi[w]) continue;
             int64_t delta = P->lng[A][bin_index(P, w, eA, mA)] -
@@ -445,28 +454,93 @@ OR_EXPORT int64_t or_exchange(or_rewl *P, int64_t r) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Averaging of one window's walkers (the per-window variant): in every bin  */
+/* some walker of the window has visited (ln g > 0), all walkers of the      */
+/* window take floor(mean over those walkers of ln g); other bins stay 0.   */
+/* ------------------------------------------------------------------------ */
+static void average_window(or_rewl *P, int w) {
+    int64_t nb = bins_of(P, w);
+    for (int64_t i = 0; i < nb; ++i) {
+        __int128 sum = 0;
+        int n = 0;
+        for (int a = 0; a < P->W; ++a) {
+            int64_t v = P->lng[w * P->W + a][i];
+            if (v > 0) {
+                sum += v;
+                n += 1;
+            }
+        }
+        if (n == 0) continue;
+        int64_t avg = (int64_t)(sum / n);
+        for (int a = 0; a < P->W; ++a) P->lng[w * P->W + a][i] = avg;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* D-9  Interval boundary: latch per-walker flatness; when every walker of   */
 /* the simulation is flat, all move to the next stage together (Sec. 2):     */
 /* ln f halves (f -> sqrt f), H is reset to zero, g is kept.  Flatness at the */
 /* last stage K ends the run.  Otherwise an exchange round follows.          */
+/* Per-window variant (sync = 1): a window whose walkers are all flat       */
+/* averages their ln g and moves to its next stage alone (its last stage    */
+/* ends it; its walkers then stop); the run ends when every window has     */
+/* ended; pairs with an ended window do not exchange.                       */
 /* ------------------------------------------------------------------------ */
+static void reset_window(or_rewl *P, int w) {
+    for (int a = 0; a < P->W; ++a) {
+        int g = w * P->W + a;
+        memset(P->H[g], 0, sizeof(uint64_t) * (size_t)bins_of(P, w));
+        P->flag[g] = 0;
+    }
+}
+
 OR_EXPORT void or_boundary(or_rewl *P) {
     if (P->done) return;
-    int all = 1;
-    for (int g = 0; g < P->nwalk; ++g) {
-        if (!P->flag[g]) P->flag[g] = (uint8_t)or_is_flat(P, g);
-        all &= P->flag[g];
-    }
-    if (all) {
-        if (P->s == P->K) {
+    if (P->sync == 0) {
+        int all = 1;
+        for (int g = 0; g < P->nwalk; ++g) {
+            if (!P->flag[g]) P->flag[g] = (uint8_t)or_is_flat(P, g);
+            all &= P->flag[g];
+        }
+        if (all) {
+            if (P->s == P->K) {
+                P->done = 1;
+                for (int w = 0; w < P->n_win; ++w) P->wdone[w] = 1;
+                P->r += 1;
+                return;
+            }
+            P->s += 1;
+            for (int w = 0; w < P->n_win; ++w) {
+                P->sw[w] = P->s;
+                reset_window(P, w);
+            }
+        }
+    } else {
+        for (int g = 0; g < P->nwalk; ++g)
+            if (!P->wdone[win_of(P, g)] && !P->flag[g]) P->flag[g] = (uint8_t)or_is_flat(P, g);
+        int all_done = 1, lowest = P->K;
+        for (int w = 0; w < P->n_win; ++w) {
+            if (!P->wdone[w]) {
+                int all = 1;
+                for (int a = 0; a < P->W; ++a) all &= P->flag[w * P->W + a];
+                if (all) {
+                    average_window(P, w);
+                    if (P->sw[w] == P->K) {
+                        P->wdone[w] = 1;
+                    } else {
+                        P->sw[w] += 1;
+                        reset_window(P, w);
+                    }
+                }
+            }
+            all_done &= P->wdone[w];
+            if (P->sw[w] < lowest) lowest = P->sw[w];
+        }
+        P->s = lowest;
+        if (all_done) {
             P->done = 1;
             P->r += 1;
             return;
-        }
-        P->s += 1;
-        for (int g = 0; g < P->nwalk; ++g) {
-            memset(P->H[g], 0, sizeof(uint64_t) * (size_t)bins_of(P, win_of(P, g)));
-            P->flag[g] = 0;
         }
     }
     or_exchange(P, P->r);
@@ -526,9 +600,24 @@ OR_EXPORT void or_set_walker(or_rewl *P, int g, const int64_t *lng,
     }
 }
 
-/* Set the stage index s (ln f = 2^-s) and clear the flatness latches; used by
- * statistical tests that run the walk at a fixed, negligible ln f. */
+/* Set the stage index s (ln f = 2^-s) of every window and clear the flatness
+ * latches; used by statistical tests that run the walk at a fixed, negligible
+ * ln f. */
 OR_EXPORT void or_set_stage(or_rewl *P, int s) {
     P->s = s;
+    for (int w = 0; w < P->n_win; ++w) P->sw[w] = s;
     for (int g = 0; g < P->nwalk; ++g) P->flag[g] = 0;
+}
+
+/* Choose how stages advance (before or_init): 0 = all windows together (the
+ * paper, Sec. 2), 1 = each window alone, averaging its walkers' ln g. */
+OR_EXPORT int or_set_sync(or_rewl *P, int sync) {
+    if (sync != 0 && sync != 1) return -1;
+    P->sync = sync;
+    return 0;
+}
+
+OR_EXPORT void or_window_state(const or_rewl *P, int w, int *s, int *done) {
+    *s = P->sw[w];
+    *done = P->wdone[w];
 }

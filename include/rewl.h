@@ -67,8 +67,21 @@ typedef struct {
                                     exchange rounds; >= 1 */
     uint64_t seed;               /* Philox key */
     int32_t init;                /* 0: spins Bernoulli(1/2) from Philox; 1: all +1 */
-    int32_t reserved;            /* must be 0 */
+    int32_t stage_sync;          /* REWL_SYNC_PROBLEM (the paper) or REWL_SYNC_WINDOW */
 } rewl_problem;
+
+/* How ln f is refined (rewl_problem.stage_sync).
+ *   REWL_SYNC_PROBLEM: once every walker of the problem is flat, all windows
+ *     move to the next stage together (Sec. 2); flatness at the last stage
+ *     ends the problem.
+ *   REWL_SYNC_WINDOW: a window whose walkers are all flat first averages their
+ *     ln g -- in every bin some walker of the window has visited, all walkers
+ *     take floor(mean over the walkers that visited it), other bins stay 0 --
+ *     and moves to its next stage alone; its last stage ends it, after which
+ *     its walkers make no trials and its window pairs do not exchange; the
+ *     problem ends with its last window.  (The common REWL form the paper
+ *     cites, Sec. 1; not the paper's own runs.) */
+enum { REWL_SYNC_PROBLEM = 0, REWL_SYNC_WINDOW = 1 };
 
 /* Execution form and tuning.  None of these change results. */
 enum { REWL_FORM_BATCHED = 0, REWL_FORM_PLAIN = 1 };
@@ -134,10 +147,17 @@ rewl_status rewl_sweep(rewl_plan* plan, int64_t n_trials);
 rewl_status rewl_reduce_lnf(rewl_plan* plan);
 rewl_status rewl_exchange(rewl_plan* plan);
 
-/* Per problem: stage s, done flag, trials made per walker.  Arrays of
- * n_problems entries; any may be NULL.  Synchronises. */
+/* Per problem: stage s (the lowest stage of its windows), done flag, trials
+ * made per walker of its first window.  Arrays of n_problems entries; any may
+ * be NULL.  Synchronises. */
 rewl_status rewl_query(rewl_plan* plan, int32_t* stage_out, int32_t* done_out,
                        int64_t* trials_out);
+
+/* Per window of problem prob (arrays of n_windows): the stage index (ln f =
+ * 2^-stage), whether the window has finished, and its walkers' trial count.
+ * With REWL_SYNC_PROBLEM all windows share one stage.  Synchronises. */
+rewl_status rewl_query_windows(rewl_plan* plan, int32_t prob, int32_t* stage_out, int32_t* done_out,
+                               int64_t* trials_out);
 
 /* State of walker a of window w of problem prob.  lng and H (nullable) get the
  * window table, (E_hi - E_lo + 1) x (N + 1) row-major by (e - E_lo, m), with

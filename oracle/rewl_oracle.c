@@ -482,9 +482,9 @@ static void average_window(or_rewl *P, int w) {
 /* ln f halves (f -> sqrt f), H is reset to zero, g is kept.  Flatness at the */
 /* last stage K ends the run.  Otherwise an exchange round follows.          */
 /* Per-window variant (sync = 1): a window whose walkers are all flat       */
-/* averages their ln g and moves to its next stage alone (its last stage    */
-/* ends it; its walkers then stop); the run ends when every window has     */
-/* ended; pairs with an ended window do not exchange.                       */
+/* averages their ln g, clears their H and moves to its next stage alone    */
+/* (its last stage ends it; its walkers then stop); the run ends when every */
+/* window has ended; pairs with an ended window do not exchange.            */
 /* ------------------------------------------------------------------------ */
 static void reset_window(or_rewl *P, int w) {
     for (int a = 0; a < P->W; ++a) {
@@ -524,9 +524,13 @@ OR_EXPORT void or_boundary(or_rewl *P) {
                 int all = 1;
                 for (int a = 0; a < P->W; ++a) all &= P->flag[w * P->W + a];
                 if (all) {
+                    /* the averaged tables are no longer the ones the visit
+                     * counts of this stage describe: H restarts in both cases */
                     average_window(P, w);
                     if (P->sw[w] == P->K) {
                         P->wdone[w] = 1;
+                        for (int a = 0; a < P->W; ++a)
+                            memset(P->H[w * P->W + a], 0, sizeof(uint64_t) * (size_t)bins_of(P, w));
                     } else {
                         P->sw[w] += 1;
                         reset_window(P, w);

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "librewl.so")
 REWL_OK, REWL_EINVAL, REWL_ENOMEM, REWL_EDEVICE, REWL_ESTATE, REWL_EOVERFLOW, REWL_ENOTREADY = \
     0, -1, -2, -3, -4, -5, -6
 FORM_BATCHED, FORM_PLAIN = 0, 1
+SYNC_PROBLEM, SYNC_WINDOW = 0, 1
 NBUF = 3
 
 
@@ -36,7 +37,7 @@ class _Problem(C.Structure):
     _fields_ = [("L", C.c_int32), ("n_windows", C.c_int32), ("overlap_num", C.c_int32),
                 ("overlap_den", C.c_int32), ("walkers_per_window", C.c_int32), ("k_final", C.c_int32),
                 ("flat_num", C.c_int32), ("flat_den", C.c_int32), ("interval", C.c_int64),
-                ("seed", C.c_uint64), ("init", C.c_int32), ("reserved", C.c_int32)]
+                ("seed", C.c_uint64), ("init", C.c_int32), ("stage_sync", C.c_int32)]
 
 
 class _Tuning(C.Structure):
@@ -69,6 +70,7 @@ def lib():
             "rewl_reduce_lnf": ([P], C.c_int),
             "rewl_exchange": ([P], C.c_int),
             "rewl_query": ([P, P, P, P], C.c_int),
+            "rewl_query_windows": ([P, C.c_int32, P, P, P], C.c_int),
             "rewl_read_walker": ([P, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_size_t, P,
                                   C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int),
             "rewl_lnz_forward": ([P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_int64,
@@ -105,7 +107,10 @@ def _check(status):
 
 @dataclass
 class Problem:
-    """One REWL simulation (Sec. 2 of the paper; defaults: 80 % flatness)."""
+    """One REWL simulation (Sec. 2 of the paper; defaults: 80 % flatness).
+
+    stage_sync: SYNC_PROBLEM (all windows refine ln f together, the paper) or
+    SYNC_WINDOW (each window averages its walkers' ln g and refines alone)."""
     L: int
     n_windows: int = 1
     overlap: tuple = (3, 4)
@@ -115,11 +120,12 @@ class Problem:
     interval: int = 10_000
     seed: int = 0
     init: int = 0
+    stage_sync: int = SYNC_PROBLEM
 
     def _c(self):
         return _Problem(self.L, self.n_windows, self.overlap[0], self.overlap[1], self.walkers_per_window,
                         self.k_final, self.flat[0], self.flat[1], self.interval,
-                        self.seed & 0xFFFFFFFFFFFFFFFF, self.init, 0)
+                        self.seed & 0xFFFFFFFFFFFFFFFF, self.init, self.stage_sync)
 
     @property
     def N(self):
@@ -197,6 +203,15 @@ class Plan:
         dn = np.zeros(n, np.int32)
         tr = np.zeros(n, np.int64)
         _check(lib().rewl_query(self._h, st.ctypes.data, dn.ctypes.data, tr.ctypes.data))
+        return {"stage": st, "done": dn.astype(bool), "trials": tr}
+
+    def query_windows(self, prob=0):
+        """Per window of problem prob: stage, done, trials per walker."""
+        n = self.problems[prob].n_windows
+        st = np.zeros(n, np.int32)
+        dn = np.zeros(n, np.int32)
+        tr = np.zeros(n, np.int64)
+        _check(lib().rewl_query_windows(self._h, prob, st.ctypes.data, dn.ctypes.data, tr.ctypes.data))
         return {"stage": st, "done": dn.astype(bool), "trials": tr}
 
     def set_tuning(self, tuning):

@@ -54,8 +54,9 @@ struct rewl_plan {
     size_t sizes[REWL_NBUF] = {0, 0, 0};
     // STATE buffer offsets
     size_t off_wd = 0, off_pd = 0, off_pairs = 0, off_e = 0, off_m = 0, off_t = 0, off_te = 0,
-           off_nseen = 0, off_flag = 0, off_scan = 0, off_stage = 0, off_done = 0, off_rnd = 0,
-           off_tstage = 0, off_xr = 0, off_xon = 0, off_adv = 0, off_lngb = 0, off_tseen = 0, off_cnt = 0;
+           off_nseen = 0, off_flag = 0, off_scan = 0, off_stage = 0, off_wdone = 0, off_tstage = 0, off_adv = 0,
+           off_lngb = 0, off_tseen = 0, off_done = 0, off_rnd = 0, off_xr = 0, off_xon = 0, off_cnt = 0;
+    int32_t n_win = 0;  // windows over all problems
     // binding
     bool bound = false;
     bool broken = false;
@@ -104,7 +105,8 @@ rewl_status validate(const rewl_problem& q, int idx) {
     if (q.flat_den < 1 || q.flat_num < 0 || q.flat_num > q.flat_den) return bad("flatness must be num/den <= 1");
     if (q.interval < 1) return bad("interval must be >= 1");
     if (q.init != 0 && q.init != 1) return bad("init must be 0 or 1");
-    if (q.reserved != 0) return bad("reserved must be 0");
+    if (q.stage_sync != REWL_SYNC_PROBLEM && q.stage_sync != REWL_SYNC_WINDOW)
+        return bad("stage_sync must be REWL_SYNC_PROBLEM or REWL_SYNC_WINDOW");
     const int N = q.L * q.L;
     for (int i = 0; i < q.n_windows; ++i) {
         int lo, hi;
@@ -144,18 +146,20 @@ DevState make_state(rewl_plan* P) {
     S.flag = reinterpret_cast<uint32_t*>(st + P->off_flag);
     S.scan = reinterpret_cast<uint32_t*>(st + P->off_scan);
     S.stage = reinterpret_cast<int32_t*>(st + P->off_stage);
-    S.done = reinterpret_cast<int32_t*>(st + P->off_done);
-    S.rnd = reinterpret_cast<int64_t*>(st + P->off_rnd);
+    S.wdone = reinterpret_cast<int32_t*>(st + P->off_wdone);
     S.tstage = reinterpret_cast<int64_t*>(st + P->off_tstage);
-    S.xr = reinterpret_cast<int64_t*>(st + P->off_xr);
-    S.xon = reinterpret_cast<int32_t*>(st + P->off_xon);
     S.adv = reinterpret_cast<int32_t*>(st + P->off_adv);
     S.lngb = reinterpret_cast<int64_t*>(st + P->off_lngb);
     S.tseen = reinterpret_cast<int64_t*>(st + P->off_tseen);
+    S.done = reinterpret_cast<int32_t*>(st + P->off_done);
+    S.rnd = reinterpret_cast<int64_t*>(st + P->off_rnd);
+    S.xr = reinterpret_cast<int64_t*>(st + P->off_xr);
+    S.xon = reinterpret_cast<int32_t*>(st + P->off_xon);
     S.counters = reinterpret_cast<int32_t*>(st + P->off_cnt);
     S.n_walk = P->n_walk;
     S.n_prob = static_cast<int32_t>(P->pd.size());
     S.n_pairs = static_cast<int32_t>(P->pairs.size());
+    S.n_win = P->n_win;
     return S;
 }
 
@@ -193,6 +197,7 @@ rewl_status enqueue_sweep(rewl_plan* P, int64_t n, int ev_slot = -1) {
 rewl_status enqueue_boundary(rewl_plan* P) {
     HIPCHK(P, launch_flat(P->S, P->stream), "flatness launch");
     HIPCHK(P, launch_stage(P->S, P->stream), "stage launch");
+    HIPCHK(P, launch_average(P->S, P->stream), "average launch");
     HIPCHK(P, launch_snapshot(P->S, P->stream), "snapshot launch");
     return REWL_OK;
 }
@@ -240,58 +245,98 @@ rewl_status run_interval_plain(rewl_plan* P) {
         }
     }
     HIPCHK(P, launch_flat(P->S, P->stream), "flatness launch");
-    const size_t np = P->pd.size();
-    std::vector<int32_t> stage, done, xon, adv;
-    std::vector<int64_t> rnd, tstage, xr, t, lngb, tseen;
+    const size_t np = P->pd.size(), nwin = static_cast<size_t>(P->n_win);
+    std::vector<int32_t> stage, wdone, adv, done, xon;
+    std::vector<int64_t> tstage, lngb, tseen, rnd, xr, t;
     std::vector<uint32_t> flag;
     rewl_status s;
-    if ((s = d2h(P, stage, P->off_stage, np)) || (s = d2h(P, done, P->off_done, np)) ||
-        (s = d2h(P, rnd, P->off_rnd, np)) || (s = d2h(P, tstage, P->off_tstage, np)) ||
-        (s = d2h(P, xr, P->off_xr, np)) || (s = d2h(P, xon, P->off_xon, np)) ||
-        (s = d2h(P, lngb, P->off_lngb, np)) || (s = d2h(P, tseen, P->off_tseen, np)) ||
+    if ((s = d2h(P, stage, P->off_stage, nwin)) || (s = d2h(P, wdone, P->off_wdone, nwin)) ||
+        (s = d2h(P, tstage, P->off_tstage, nwin)) || (s = d2h(P, lngb, P->off_lngb, nwin)) ||
+        (s = d2h(P, tseen, P->off_tseen, nwin)) || (s = d2h(P, done, P->off_done, np)) ||
+        (s = d2h(P, rnd, P->off_rnd, np)) || (s = d2h(P, xr, P->off_xr, np)) || (s = d2h(P, xon, P->off_xon, np)) ||
         (s = d2h(P, t, P->off_t, P->n_walk)) || (s = d2h(P, flag, P->off_flag, P->n_walk)))
         return s;
     HIPCHK(P, hipStreamSynchronize(P->stream), "plain boundary sync");
     bool overflow = false;
-    adv.assign(np, 0);
+    adv.assign(nwin, 0);
     for (size_t p = 0; p < np; ++p) {
         const PDesc& q = P->pd[p];
         if (done[p]) {
             xon[p] = 0;
             continue;
         }
-        const int64_t tnow = t[q.walker_off];
-        const int64_t dt = tnow - tseen[p];
-        const int sh = q.K - stage[p];
-        const int64_t room = ((static_cast<int64_t>(1) << 62) - lngb[p]) >> sh;
-        if (dt > room) overflow = true;
-        else lngb[p] += dt << sh;
-        tseen[p] = tnow;
-        const int nw = q.nwin * q.W;
-        bool all = true;
-        for (int i = 0; i < nw; ++i) all = all && flag[q.walker_off + i] != 0;
+        for (int w = 0; w < q.nwin; ++w) {
+            const int wi = q.win_off + w;
+            if (wdone[wi]) continue;
+            const int64_t tnow = t[q.walker_off + w * q.W];
+            const int64_t dt = tnow - tseen[wi];
+            const int sh = q.K - stage[wi];
+            const int64_t room = ((static_cast<int64_t>(1) << 62) - lngb[wi]) >> sh;
+            if (dt > room) overflow = true;
+            else lngb[wi] += dt << sh;
+            tseen[wi] = tnow;
+        }
         const int64_t r = rnd[p];
-        if (all) {
-            if (stage[p] == q.K) {
-                done[p] = 1;
-                xon[p] = 0;
-                rnd[p] = r + 1;
-                continue;
+        bool ended = false;
+        if (q.sync == REWL_SYNC_PROBLEM) {
+            const int nw = q.nwin * q.W;
+            bool all = true;
+            for (int i = 0; i < nw; ++i) all = all && flag[q.walker_off + i] != 0;
+            if (all) {
+                const bool last = stage[q.win_off] == q.K;
+                for (int w = 0; w < q.nwin; ++w) {
+                    const int wi = q.win_off + w;
+                    if (last) {
+                        wdone[wi] = 1;
+                    } else {
+                        stage[wi] += 1;
+                        tstage[wi] = t[q.walker_off];
+                        adv[wi] = 1;
+                    }
+                }
+                if (last) ended = true;
+                else
+                    for (int i = 0; i < nw; ++i) flag[q.walker_off + i] = 0;
             }
-            stage[p] += 1;
-            tstage[p] = tnow;
-            adv[p] = 1;
-            for (int i = 0; i < nw; ++i) flag[q.walker_off + i] = 0;
+        } else {
+            bool all_done = true;
+            for (int w = 0; w < q.nwin; ++w) {
+                const int wi = q.win_off + w;
+                if (!wdone[wi]) {
+                    const int g0 = q.walker_off + w * q.W;
+                    bool all = true;
+                    for (int a = 0; a < q.W; ++a) all = all && flag[g0 + a] != 0;
+                    if (all) {
+                        adv[wi] = 1;
+                        if (stage[wi] == q.K) {
+                            wdone[wi] = 1;
+                        } else {
+                            stage[wi] += 1;
+                            tstage[wi] = t[g0];
+                            for (int a = 0; a < q.W; ++a) flag[g0 + a] = 0;
+                        }
+                    }
+                }
+                all_done = all_done && wdone[wi] != 0;
+            }
+            ended = all_done;
+        }
+        if (ended) {
+            done[p] = 1;
+            xon[p] = 0;
+            rnd[p] = r + 1;
+            continue;
         }
         xr[p] = r;
         xon[p] = 1;
         rnd[p] = r + 1;
     }
-    if ((s = h2d(P, stage, P->off_stage)) || (s = h2d(P, done, P->off_done)) || (s = h2d(P, rnd, P->off_rnd)) ||
-        (s = h2d(P, tstage, P->off_tstage)) || (s = h2d(P, xr, P->off_xr)) || (s = h2d(P, xon, P->off_xon)) ||
-        (s = h2d(P, lngb, P->off_lngb)) || (s = h2d(P, tseen, P->off_tseen)) || (s = h2d(P, flag, P->off_flag)) ||
-        (s = h2d(P, adv, P->off_adv)))
+    if ((s = h2d(P, stage, P->off_stage)) || (s = h2d(P, wdone, P->off_wdone)) ||
+        (s = h2d(P, tstage, P->off_tstage)) || (s = h2d(P, adv, P->off_adv)) || (s = h2d(P, lngb, P->off_lngb)) ||
+        (s = h2d(P, tseen, P->off_tseen)) || (s = h2d(P, done, P->off_done)) || (s = h2d(P, rnd, P->off_rnd)) ||
+        (s = h2d(P, xr, P->off_xr)) || (s = h2d(P, xon, P->off_xon)) || (s = h2d(P, flag, P->off_flag)))
         return s;
+    HIPCHK(P, launch_average(P->S, P->stream), "average launch");
     HIPCHK(P, launch_snapshot(P->S, P->stream), "snapshot launch");
     if (overflow) {
         std::vector<int32_t> cnt;
@@ -376,6 +421,8 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
         d.seed = q.seed;
         d.walker_off = static_cast<int32_t>(walker);
         d.init = q.init;
+        d.win_off = P->n_win;
+        d.sync = q.stage_sync;
         P->pd.push_back(d);
         P->l_max = std::max(P->l_max, q.L);
         std::vector<int> los, his;
@@ -395,6 +442,7 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
                 wd.gid = w * q.walkers_per_window + a;
                 wd.ntm = static_cast<uint32_t>((d.N + 1 + TILE_M - 1) / TILE_M);
                 wd.nbins = static_cast<uint32_t>((hi - lo + 1 + TILE_E - 1) / TILE_E) * wd.ntm * TILE_BINS;
+                wd.gwin = P->n_win + w;
                 P->wd.push_back(wd);
                 bins += wd.nbins;
                 words += static_cast<uint64_t>(q.L) * d.row_words;
@@ -404,6 +452,7 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
         }
         P->lo.push_back(los);
         P->hi.push_back(his);
+        P->n_win += q.n_windows;
         if (walker >= (1ll << 31) || words >= (1ull << 32)) {
             delete P;
             return fail(REWL_EINVAL, "too many walkers for one plan");
@@ -430,15 +479,17 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
     P->off_nseen = take(nw * 4);
     P->off_flag = take(nw * 4);
     P->off_scan = take(nw * 4);
-    P->off_stage = take(np * 4);
+    const size_t nwn = static_cast<size_t>(P->n_win);
+    P->off_stage = take(nwn * 4);
+    P->off_wdone = take(nwn * 4);
+    P->off_tstage = take(nwn * 8);
+    P->off_adv = take(nwn * 4);
+    P->off_lngb = take(nwn * 8);
+    P->off_tseen = take(nwn * 8);
     P->off_done = take(np * 4);
     P->off_rnd = take(np * 8);
-    P->off_tstage = take(np * 8);
     P->off_xr = take(np * 8);
     P->off_xon = take(np * 4);
-    P->off_adv = take(np * 4);
-    P->off_lngb = take(np * 8);
-    P->off_tseen = take(np * 8);
     P->off_cnt = take(16);
     P->sizes[REWL_BUF_TABLES] = align_up(2 * bins * sizeof(int64_t), A);
     P->sizes[REWL_BUF_SPINS] = align_up(words * 4, A);
@@ -611,16 +662,40 @@ rewl_status rewl_query(rewl_plan* P, int32_t* stage_out, int32_t* done_out, int6
     const size_t np = P->pd.size();
     std::vector<int32_t> stage, done, cnt;
     std::vector<int64_t> t;
-    if ((s = d2h(P, stage, P->off_stage, np)) || (s = d2h(P, done, P->off_done, np)) ||
+    if ((s = d2h(P, stage, P->off_stage, static_cast<size_t>(P->n_win))) || (s = d2h(P, done, P->off_done, np)) ||
         (s = d2h(P, t, P->off_t, P->n_walk)) || (s = d2h(P, cnt, P->off_cnt, 4)))
         return s;
     HIPCHK(P, hipStreamSynchronize(P->stream), "query sync");
     for (size_t p = 0; p < np; ++p) {
-        if (stage_out) stage_out[p] = stage[p];
+        const PDesc& q = P->pd[p];
+        int lowest = stage[q.win_off];
+        for (int w = 1; w < q.nwin; ++w) lowest = std::min(lowest, stage[q.win_off + w]);
+        if (stage_out) stage_out[p] = lowest;
         if (done_out) done_out[p] = done[p];
         if (trials_out) trials_out[p] = t[P->pd[p].walker_off];
     }
     if (cnt[1] & ERR_OVERFLOW) return fail(REWL_EOVERFLOW, "ln g would exceed 2^62 units");
+    return REWL_OK;
+}
+
+rewl_status rewl_query_windows(rewl_plan* P, int32_t prob, int32_t* stage_out, int32_t* done_out,
+                               int64_t* trials_out) {
+    rewl_status s = usable(P);
+    if (s != REWL_OK) return s;
+    if (prob < 0 || prob >= static_cast<int32_t>(P->pd.size())) return fail(REWL_EINVAL, "problem out of range");
+    const PDesc& q = P->pd[prob];
+    std::vector<int32_t> stage, wdone;
+    std::vector<int64_t> t;
+    const size_t nwn = static_cast<size_t>(P->n_win);
+    if ((s = d2h(P, stage, P->off_stage, nwn)) || (s = d2h(P, wdone, P->off_wdone, nwn)) ||
+        (s = d2h(P, t, P->off_t, P->n_walk)))
+        return s;
+    HIPCHK(P, hipStreamSynchronize(P->stream), "query sync");
+    for (int w = 0; w < q.nwin; ++w) {
+        if (stage_out) stage_out[w] = stage[q.win_off + w];
+        if (done_out) done_out[w] = wdone[q.win_off + w];
+        if (trials_out) trials_out[w] = t[q.walker_off + w * q.W];
+    }
     return REWL_OK;
 }
 
@@ -655,10 +730,10 @@ rewl_status rewl_read_walker(rewl_plan* P, int32_t prob, int32_t w, int32_t a, i
                                  nwords * 4, hipMemcpyDeviceToHost, P->stream), "spin read");
     }
     if ((s = d2h(P, ev, P->off_e, P->n_walk)) || (s = d2h(P, mv, P->off_m, P->n_walk)) ||
-        (s = d2h(P, tv, P->off_t, P->n_walk)) || (s = d2h(P, stage, P->off_stage, P->pd.size())))
+        (s = d2h(P, tv, P->off_t, P->n_walk)) || (s = d2h(P, stage, P->off_stage, static_cast<size_t>(P->n_win))))
         return s;
     HIPCHK(P, hipStreamSynchronize(P->stream), "walker read sync");
-    const int sh = q.K - stage[prob];
+    const int sh = q.K - stage[d.gwin];
     if (lng || H)
         for (int er = 0; er < nE; ++er)
             for (int mm = 0; mm < nM; ++mm) {
@@ -886,7 +961,7 @@ extern "C" rewl_status rewl_set_tuning(rewl_plan* P, const rewl_tuning* tuning) 
 }
 
 namespace {
-constexpr uint64_t SAVE_MAGIC = 0x3130574C57455232ull;  // "2REWLW01"
+constexpr uint64_t SAVE_MAGIC = 0x3230574C57455232ull;  // "2REWLW02": per-window stage state
 struct SaveHeader {
     uint64_t magic;
     uint64_t n_problems;

@@ -34,6 +34,7 @@ struct WDesc {
     int32_t gid;         // walker id within the problem: win * W + a
     uint32_t ntm;        // tiles per energy row = ceil((N + 1) / 4)
     uint32_t nbins;      // bins of its tiled table = ceil((hi - lo + 1) / 4) * ntm * 16
+    int32_t gwin;        // window index over all problems of the plan
 };
 
 // Static description of one problem.
@@ -43,6 +44,8 @@ struct PDesc {
     uint64_t seed;
     int32_t walker_off;  // first global walker index
     int32_t init;
+    int32_t win_off;     // first global window index
+    int32_t sync;        // 0: all windows change stage together; 1: each window alone
 };
 
 // A window pair (w, w+1) of one problem that may exchange configurations.
@@ -66,21 +69,24 @@ struct DevState {
     uint32_t* nseen;  // bins with ln g > 0
     uint32_t* flag;   // flat in the current stage (latched)
     uint32_t* scan;   // chunk where the last flatness scan failed (a hint)
-    // per problem
-    int32_t* stage;
-    int32_t* done;
-    int64_t* rnd;     // boundaries passed
-    int64_t* tstage;  // trial count at the start of the stage
-    int64_t* xr;      // exchange round of the boundary just closed
-    int32_t* xon;     // that boundary exchanges
-    int32_t* adv;     // the problem moved to the next stage at the boundary just closed
+    // per window (index gwin)
+    int32_t* stage;   // ln f = 2^-stage
+    int32_t* wdone;   // the window has finished its last stage; its walkers stop
+    int64_t* tstage;  // trial count of its walkers at the start of the stage
+    int32_t* adv;     // the window ended a stage at the boundary just closed
     int64_t* lngb;    // upper bound of any ln g entry (units), for the int64 headroom guard
     int64_t* tseen;   // trial count at the last boundary
+    // per problem
+    int32_t* done;    // every window has finished
+    int64_t* rnd;     // boundaries passed
+    int64_t* xr;      // exchange round of the boundary just closed
+    int32_t* xon;     // that boundary exchanges
     // misc
     int32_t* counters;  // [0] walkers outside their window (entry), [1] error bits
     int64_t n_walk;
     int32_t n_prob;
     int32_t n_pairs;
+    int32_t n_win;      // windows over all problems
 };
 
 enum : int32_t { ERR_OVERFLOW = 1 };
@@ -110,6 +116,7 @@ hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int
 hipError_t sweep_setup();
 hipError_t launch_flat(const DevState& S, hipStream_t st);
 hipError_t launch_stage(const DevState& S, hipStream_t st);
+hipError_t launch_average(const DevState& S, hipStream_t st);
 hipError_t launch_snapshot(const DevState& S, hipStream_t st);
 hipError_t launch_exchange(const DevState& S, hipStream_t st);
 

@@ -166,17 +166,21 @@ __global__ void k_init(DevState S) {
     S.nseen[g] = 0;
     S.flag[g] = 0;
     S.scan[g] = 0;
+    if (d.gid % P.W == 0) {  // first walker of its window
+        const int wi = d.gwin;
+        S.stage[wi] = 0;
+        S.wdone[wi] = 0;
+        S.tstage[wi] = 0;
+        S.adv[wi] = 0;
+        S.lngb[wi] = 0;
+        S.tseen[wi] = 0;
+    }
     if (d.gid == 0) {
         const int p = d.prob;
-        S.stage[p] = 0;
         S.done[p] = 0;
         S.rnd[p] = 0;
-        S.tstage[p] = 0;
         S.xr[p] = 0;
         S.xon[p] = 0;
-        S.lngb[p] = 0;
-        S.tseen[p] = 0;
-        S.adv[p] = 0;
     }
 }
 
@@ -301,10 +305,10 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
                                              int64_t n_trials) {
     const WDesc d = S.wd[g];
     const int p = d.prob;
-    if (S.done[p]) return;
+    if (S.wdone[d.gwin]) return;  // the window (or the whole problem) has finished
     const PDesc P = S.pd[p];
     const int L = P.L, K = P.K, rw = P.row_words;
-    const int s = S.stage[p];
+    const int s = S.stage[d.gwin];
     const int64_t inc = static_cast<int64_t>(1) << (K - s);
     const int lo = d.lo, hi = d.hi;
     const uint32_t ntm = d.ntm;
@@ -446,11 +450,11 @@ __global__ void __launch_bounds__(256) k_flat(DevState S) {
     if (g >= S.n_walk) return;
     const WDesc d = S.wd[g];
     const int p = d.prob;
-    if (S.done[p] || S.flag[g]) return;
+    if (S.wdone[d.gwin] || S.flag[g]) return;
     const PDesc P = S.pd[p];
-    const int sh = P.K - S.stage[p];
+    const int sh = P.K - S.stage[d.gwin];
     const uint64_t n = S.nseen[g];
-    const uint64_t sum = static_cast<uint64_t>(S.t[g] - S.tstage[p]);
+    const uint64_t sum = static_cast<uint64_t>(S.t[g] - S.tstage[d.gwin]);
     if (n == 0) return;
     const int64_t* tab = S.lng + d.table_off;
     const int64_t* snp = S.snap + d.table_off;
@@ -489,54 +493,149 @@ __global__ void __launch_bounds__(256) k_flat(DevState S) {
 }
 
 // ------------------------------------------------------------------ stage
-// Per problem: when every walker is flat, all move to the next stage together
-// (ln f halves; H restarts from zero through a new snapshot of ln g); flatness
-// at the last stage ends the problem.  Otherwise the boundary's exchange
-// round is armed.  Also guards the int64 headroom of ln g.
+// Per problem, at an interval boundary.  sync 0 (the paper, Sec. 2): when
+// every walker is flat all windows move to the next stage together (ln f
+// halves; H restarts from zero through a new snapshot of ln g); flatness at
+// the last stage ends the problem.  sync 1: each window whose walkers are all
+// flat averages their ln g (k_average) and moves on alone; its last stage
+// ends it and its walkers stop; the problem ends with its last window.
+// Unless the problem has ended, the boundary's exchange round is armed.
+// Also guards the int64 headroom of ln g per window.
 __global__ void k_stage(DevState S) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= S.n_prob) return;
-    S.adv[p] = 0;
+    const PDesc P = S.pd[p];
+    for (int w = 0; w < P.nwin; ++w) S.adv[P.win_off + w] = 0;
     if (S.done[p]) {
         S.xon[p] = 0;
         return;
     }
-    const PDesc P = S.pd[p];
     // every ln g entry is at most the sum of all increments made so far
-    const int64_t tnow = S.t[P.walker_off];
-    const int64_t dt = tnow - S.tseen[p];
-    const int sh = P.K - S.stage[p];
-    const int64_t room = ((static_cast<int64_t>(1) << 62) - S.lngb[p]) >> sh;
-    if (dt > room) atomicOr(&S.counters[1], ERR_OVERFLOW);
-    else S.lngb[p] += dt << sh;
-    S.tseen[p] = tnow;
-    const int nw = P.nwin * P.W;
-    bool all = true;
-    for (int i = 0; i < nw; ++i) all = all && (S.flag[P.walker_off + i] != 0);
+    for (int w = 0; w < P.nwin; ++w) {
+        const int wi = P.win_off + w;
+        if (S.wdone[wi]) continue;
+        const int64_t tnow = S.t[P.walker_off + w * P.W];
+        const int64_t dt = tnow - S.tseen[wi];
+        const int sh = P.K - S.stage[wi];
+        const int64_t room = ((static_cast<int64_t>(1) << 62) - S.lngb[wi]) >> sh;
+        if (dt > room) atomicOr(&S.counters[1], ERR_OVERFLOW);
+        else S.lngb[wi] += dt << sh;
+        S.tseen[wi] = tnow;
+    }
     const int64_t r = S.rnd[p];
-    if (all) {
-        if (S.stage[p] == P.K) {
-            S.done[p] = 1;
-            S.xon[p] = 0;
-            S.rnd[p] = r + 1;
-            return;
+    bool ended = false;
+    if (P.sync == 0) {
+        const int nw = P.nwin * P.W;
+        bool all = true;
+        for (int i = 0; i < nw; ++i) all = all && (S.flag[P.walker_off + i] != 0);
+        if (all) {
+            const int64_t tnow = S.t[P.walker_off];
+            const bool last = S.stage[P.win_off] == P.K;
+            for (int w = 0; w < P.nwin; ++w) {
+                const int wi = P.win_off + w;
+                if (last) {
+                    S.wdone[wi] = 1;
+                } else {
+                    S.stage[wi] += 1;
+                    S.tstage[wi] = tnow;
+                    S.adv[wi] = 1;
+                }
+            }
+            if (last) ended = true;
+            else
+                for (int i = 0; i < nw; ++i) S.flag[P.walker_off + i] = 0;
         }
-        S.stage[p] += 1;
-        S.tstage[p] = tnow;
-        S.adv[p] = 1;
-        for (int i = 0; i < nw; ++i) S.flag[P.walker_off + i] = 0;
+    } else {
+        bool all_done = true;
+        for (int w = 0; w < P.nwin; ++w) {
+            const int wi = P.win_off + w;
+            if (!S.wdone[wi]) {
+                const int g0 = P.walker_off + w * P.W;
+                bool all = true;
+                for (int a = 0; a < P.W; ++a) all = all && (S.flag[g0 + a] != 0);
+                if (all) {
+                    S.adv[wi] = 1;  // average (and, if it goes on, take a new snapshot)
+                    if (S.stage[wi] == P.K) {
+                        S.wdone[wi] = 1;
+                    } else {
+                        S.stage[wi] += 1;
+                        S.tstage[wi] = S.t[g0];
+                        for (int a = 0; a < P.W; ++a) S.flag[g0 + a] = 0;
+                    }
+                }
+            }
+            all_done = all_done && S.wdone[wi] != 0;
+        }
+        ended = all_done;
+    }
+    if (ended) {
+        S.done[p] = 1;
+        S.xon[p] = 0;
+        S.rnd[p] = r + 1;
+        return;
     }
     S.xr[p] = r;
     S.xon[p] = 1;
     S.rnd[p] = r + 1;
 }
 
-// Snapshot of ln g for the walkers of problems that just changed stage: one
+// Per-window averaging (sync 1) of a window that has just ended a stage: in
+// every bin some walker of the window has visited (ln g > 0) all its walkers
+// take floor(mean over those walkers); the other bins stay 0.  The number of
+// visited bins becomes every walker's n_seen.  One workgroup per window; the
+// walkers of a window share one tiled geometry.
+__global__ void __launch_bounds__(256) k_average(DevState S) {
+    const int wi = blockIdx.x;
+    if (wi >= S.n_win || !S.adv[wi]) return;
+    __shared__ int32_t g0s;
+    __shared__ uint32_t cnt[256];
+    if (threadIdx.x == 0) {
+        // first walker of window wi: the walkers are laid out window by window
+        int lo = 0, hi = S.n_prob - 1;
+        while (lo < hi) {  // last problem with win_off <= wi
+            const int mid = (lo + hi + 1) / 2;
+            if (S.pd[mid].win_off <= wi) lo = mid;
+            else hi = mid - 1;
+        }
+        const PDesc P = S.pd[lo];
+        g0s = P.sync == 1 ? P.walker_off + (wi - P.win_off) * P.W : -1;
+    }
+    __syncthreads();
+    const int g0 = g0s;
+    if (g0 < 0) return;
+    const WDesc d0 = S.wd[g0];
+    const int W = S.pd[d0.prob].W;
+    uint32_t seen = 0;
+    for (uint32_t i = threadIdx.x; i < d0.nbins; i += blockDim.x) {
+        unsigned __int128 sum = 0;
+        uint32_t n = 0;
+        for (int a = 0; a < W; ++a) {
+            const int64_t v = S.lng[S.wd[g0 + a].table_off + i];
+            if (v > 0) {
+                sum += static_cast<uint64_t>(v);
+                ++n;
+            }
+        }
+        if (n == 0) continue;
+        const int64_t avg = static_cast<int64_t>(sum / n);
+        for (int a = 0; a < W; ++a) S.lng[S.wd[g0 + a].table_off + i] = avg;
+        ++seen;
+    }
+    cnt[threadIdx.x] = seen;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (static_cast<int>(threadIdx.x) < o) cnt[threadIdx.x] += cnt[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (static_cast<int>(threadIdx.x) < W) S.nseen[g0 + threadIdx.x] = cnt[0];
+}
+
+// Snapshot of ln g for the walkers of windows that just ended a stage: one
 // workgroup per walker, a coalesced copy of its table.
 __global__ void __launch_bounds__(256) k_snapshot(DevState S) {
     const int64_t g = blockIdx.x;
     const WDesc d = S.wd[g];
-    if (!S.adv[d.prob]) return;
+    if (!S.adv[d.gwin]) return;
     const int64_t* src = S.lng + d.table_off;
     int64_t* dst = S.snap + d.table_off;
     for (uint32_t i = threadIdx.x; i < d.nbins; i += blockDim.x) dst[i] = src[i];
@@ -559,6 +658,7 @@ __global__ void __launch_bounds__(64) k_exchange(DevState S) {
     const int64_t r = S.xr[p];
     if ((w & 1) != static_cast<int>(r & 1)) return;
     const PDesc P = S.pd[p];
+    if (S.wdone[P.win_off + w] || S.wdone[P.win_off + w + 1]) return;  // a finished window does not exchange
     const int W = P.W;
     if (threadIdx.x == 0) {
         const uint32_t r_lo = static_cast<uint32_t>(r), r_hi = static_cast<uint32_t>(static_cast<uint64_t>(r) >> 32);
@@ -662,6 +762,12 @@ hipError_t launch_flat(const DevState& S, hipStream_t st) {
 
 hipError_t launch_stage(const DevState& S, hipStream_t st) {
     hipLaunchKernelGGL(k_stage, dim3(blocks_for(S.n_prob, 64)), dim3(64), 0, st, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_average(const DevState& S, hipStream_t st) {
+    if (S.n_win <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_average, dim3(S.n_win), dim3(256), 0, st, S);
     return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@ Fig. 5):  epsilon(E) = |ln g - ln g_exact| / ln g_exact over realizable E.
 
   python tests/long_convergence.py --config c2 --replicas 8 --seconds 900 --out gpurun_out/conv_c2
   python tests/long_convergence.py --config c2 ... --resume      # continue from the checkpoint
+  python tests/long_convergence.py --config c2 ... --resume --evaluate-now   # compare the state reached
 
 Configurations: c2 = 16x16, 8 windows (overlap 3/4) x 4 walkers, ln f -> 2^-20;
 p8w2 / p8w20 = 8x8, 3 windows (overlap 1/2) x 2 or 20 walkers, ln f -> 2^-20;
@@ -57,6 +58,8 @@ def main():
     ap.add_argument("--seconds", type=float, default=900)
     ap.add_argument("--out", default="gpurun_out/conv")
     ap.add_argument("--resume", action="store_true")
+    ap.add_argument("--evaluate-now", action="store_true",
+                    help="compare the current (unfinished) state with the exact g(E) instead of running on")
     args = ap.parse_args()
     import torch  # noqa: F401  (device memory for the plan)
     import paper_1508_02748_amd as R
@@ -82,7 +85,7 @@ def main():
         plan.init()
     t0 = time.time()
     last = t0
-    while time.time() - t0 < args.seconds:
+    while not args.evaluate_now and time.time() - t0 < args.seconds:
         plan.run(256)
         meta["intervals"] += 256
         q = plan.query()
@@ -97,7 +100,7 @@ def main():
     meta["done"] = int(q["done"].sum())
     meta["stage"] = [int(x) for x in q["stage"]]
     meta["trials_per_walker"] = [int(x) for x in q["trials"]]
-    if not q["done"].all():
+    if not q["done"].all() and not args.evaluate_now:
         with open(ck, "wb") as f:
             f.write(zlib.compress(plan.save(), 6))
         with open(meta_path, "w") as f:
@@ -153,9 +156,10 @@ def main():
                           "mean_interior": float(d[~edge].mean()), "mean_edges": float(d[edge].mean())})
             print(f"replica {r}: Eq. 5 over {both.sum()} bins: mean {d.mean():.4g}, max {d.max():.4g}", flush=True)
         res["rel_diff"] = diffs
-    with open(os.path.join(args.out, "result.json"), "w") as f:
+    name = "result.json" if q["done"].all() else "result_at_stage_%d.json" % min(meta["stage"])
+    with open(os.path.join(args.out, name), "w") as f:
         json.dump(res, f, indent=1)
-    if os.path.exists(ck):
+    if os.path.exists(ck) and q["done"].all():
         os.remove(ck)
     print(json.dumps(res["replica_mean"]), flush=True)
 

@@ -46,7 +46,7 @@ def test_plan_validation_and_windows_on_host():
     for bad in (dict(L=5), dict(L=2), dict(L=66), dict(L=16, n_windows=0), dict(L=16, overlap=(4, 4)),
                 dict(L=16, walkers_per_window=0), dict(L=16, walkers_per_window=257), dict(L=16, k_final=41),
                 dict(L=16, flat=(6, 5)), dict(L=16, interval=0), dict(L=16, init=2),
-                dict(L=16, overlap=(-1, 4)), dict(L=16, flat=(1, 0))):
+                dict(L=16, overlap=(-1, 4)), dict(L=16, flat=(1, 0)), dict(L=16, stage_sync=2)):
         st, h = create(**bad)
         assert st == R.REWL_EINVAL, bad
         assert L.rewl_last_error()

@@ -26,7 +26,7 @@ def _R():
 
 def _oracle_of(p):
     o = OracleREWL(p.L, p.n_windows, p.overlap, p.walkers_per_window, p.k_final, p.flat, p.interval,
-                   p.seed, p.init)
+                   p.seed, p.init, sync=p.stage_sync)
     o.init()
     return o
 
@@ -51,6 +51,9 @@ def compare(plan, pi, orc, tables=True, walkers=None):
     q = plan.query()
     info = orc.info()
     assert int(q["stage"][pi]) == info["stage"] and bool(q["done"][pi]) == info["done"], (q, info)
+    qw = plan.query_windows(pi)
+    for w in range(p.n_windows):
+        assert (int(qw["stage"][w]), bool(qw["done"][w])) == orc.window_state(w), (pi, w)
 
 
 def test_c1_serial_wl_full_run_bit_exact():
@@ -197,3 +200,51 @@ def test_persistent_grid_loops_over_tiles():
         o = _oracle_of(probs[i])
         o.run(6)
         compare(plan, i, o)
+
+
+def test_per_window_variant_bit_exact_batched_and_plain():
+    """REWL_SYNC_WINDOW: windows refine alone after averaging their walkers; run
+    past the point where some windows have finished and others have not."""
+    R = _R()
+    p = R.Problem(L=8, n_windows=3, overlap=(1, 2), walkers_per_window=3, k_final=5, interval=1000, seed=3,
+                  stage_sync=R.SYNC_WINDOW)
+    _say("case: per-window variant 8x8 3x3, K=5, batched and plain (the oracle ends after 3680 intervals)")
+    batched = R.Plan([p], R.Tuning(graph_intervals=4))
+    plain = R.Plan([p], R.Tuning(form=R.FORM_PLAIN))
+    batched.init()
+    plain.init()
+    orc = _oracle_of(p)
+    seen_partial = False
+    for _ in range(300):
+        batched.run(20)
+        plain.run(20)
+        orc.run(20)
+        compare(batched, 0, orc)
+        compare(plain, 0, orc)
+        ws = [orc.window_state(w)[1] for w in range(p.n_windows)]
+        seen_partial = seen_partial or (any(ws) and not all(ws))
+        if orc.info()["done"]:
+            break
+    assert orc.info()["done"] and seen_partial
+
+
+def test_mixed_sync_batch_bit_exact():
+    """Problems of both stage rules and several lattice sizes in one launch."""
+    R = _R()
+    probs = [R.Problem(L=8, n_windows=3, overlap=(1, 2), walkers_per_window=2, k_final=8, interval=1000, seed=21,
+                       stage_sync=R.SYNC_WINDOW),
+             R.Problem(L=12, n_windows=4, walkers_per_window=2, k_final=8, interval=1000, seed=22),
+             R.Problem(L=16, n_windows=4, walkers_per_window=3, k_final=8, interval=1000, seed=23,
+                       stage_sync=R.SYNC_WINDOW),
+             R.Problem(L=4, n_windows=1, walkers_per_window=4, k_final=10, interval=1000, seed=24,
+                       stage_sync=R.SYNC_WINDOW)]
+    _say("case: mixed stage rules, L in {4,8,12,16}")
+    plan = R.Plan(probs, R.Tuning(graph_intervals=5))
+    plan.init()
+    orcs = [_oracle_of(p) for p in probs]
+    for _ in range(12):
+        plan.run(25)
+        for o in orcs:
+            o.run(25)
+        for i, o in enumerate(orcs):
+            compare(plan, i, o)

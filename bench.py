@@ -48,7 +48,7 @@ VALU_PEAK_SLOTS = 256 * 64 * 2.4e9
 # HBM-side bytes per sweep launch, FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a 1 GiB
 # device copy), by (workload, replicas, walkers per workgroup, grid waves per CU); measured on
 # the current sweep kernel with rocprofv3 --pmc.  Other shapes report null.
-TRAFFIC_BYTES = {("c2", 4096, 256, 4): 38.44e9}
+TRAFFIC_BYTES = {}
 
 
 def log(*a):

@@ -35,9 +35,9 @@ C4 = dict(L=64, n_windows=64, overlap=(3, 4), walkers_per_window=4, k_final=20, 
 WORKLOADS = {
     "c2": (C2, 4096, "16x16 periodic Ising 2D-REWL (8 windows x 4 walkers, overlap 3/4, ln f 1 -> 2^-20, "
                      "80% flat, exchange every 10^4 trials)"),
-    "c3": (C3, 192, "32x32 periodic Ising 2D-REWL (16 windows x 8 walkers, overlap 3/4, ln f 1 -> 2^-24, "
+    "c3": (C3, 240, "32x32 periodic Ising 2D-REWL (16 windows x 8 walkers, overlap 3/4, ln f 1 -> 2^-24, "
                     "80% flat, exchange every 10^4 trials)"),
-    "c4": (C4, 16, "64x64 periodic Ising 2D-REWL (64 windows x 4 walkers, overlap 3/4, ln f 1 -> 2^-20, "
+    "c4": (C4, 28, "64x64 periodic Ising 2D-REWL (64 windows x 4 walkers, overlap 3/4, ln f 1 -> 2^-20, "
                    "80% flat, exchange every 10^5 trials)"),
 }
 # Algorithmic VALU issue slots per trial (full-rate 32-bit lane operations; a
@@ -48,7 +48,7 @@ VALU_PEAK_SLOTS = 256 * 64 * 2.4e9
 # HBM-side bytes per sweep launch, FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a 1 GiB
 # device copy), by (workload, replicas, walkers per workgroup, grid waves per CU); measured on
 # the current sweep kernel with rocprofv3 --pmc.  Other shapes report null.
-TRAFFIC_BYTES = {}
+TRAFFIC_BYTES = {("c2", 4096, 256, 4): 38.44e9}
 
 
 def log(*a):

@@ -18,6 +18,13 @@ namespace {
 
 constexpr int TILE = 256;
 
+// Every exponential below is of d <= 0: a term relative to the largest term of
+// its sum (or to the sum itself).  Terms with d <= -80 are skipped: e^-80 <
+// 2e-35, so even 2^32 skipped terms change a sum by less than 1e-25 of its
+// largest term, far below float64 rounding.  The branch lets a wavefront skip
+// the exponential when none of its lanes needs it.
+constexpr double CUT = -80.0;
+
 struct Geo {
     const double* lng;
     int N, e0, nE, m0, nM;
@@ -73,8 +80,8 @@ __global__ void __launch_bounds__(TILE) k_lnz_fwd(Geo geo, const double* beta, c
         __syncthreads();
         const int n = static_cast<int>(nb - base < TILE ? nb - base : TILE);
         for (int j = 0; j < n; ++j) {
-            const double x = sl[j] - b * sE[j] + bh * sM[j];
-            sum += exp(x - mx);
+            const double d = (sl[j] - b * sE[j] + bh * sM[j]) - mx;
+            if (d > CUT) sum += exp(d);
         }
     }
     if (on) lnz[gp] = mx + log(sum);
@@ -112,8 +119,9 @@ __global__ void __launch_bounds__(TILE) k_lnz_mom(Geo geo, const double* beta, c
             __syncthreads();
             const int n = static_cast<int>(nb - base < TILE ? nb - base : TILE);
             for (int j = 0; j < n; ++j) {
-                const double x = sl[j] - b * sE[j] + bh * sM[j];
-                const double p = exp(x - z);
+                const double d = (sl[j] - b * sE[j] + bh * sM[j]) - z;
+                if (!(d > CUT)) continue;
+                const double p = exp(d);
                 const double U = -sE[j] + h * sM[j];
                 if (pass == 0) {
                     s0 += p;
@@ -170,7 +178,10 @@ __global__ void __launch_bounds__(TILE) k_lnz_glng(Geo geo, const double* beta, 
         }
         __syncthreads();
         const int n = static_cast<int>(G - base < TILE ? G - base : TILE);
-        for (int j = 0; j < n; ++j) acc += sg[j] * exp(l - sb[j] * E + sbh[j] * M - sz[j]);
+        for (int j = 0; j < n; ++j) {
+            const double d = l - sb[j] * E + sbh[j] * M - sz[j];
+            if (d > CUT) acc += sg[j] * exp(d);
+        }
     }
     if (i < nb) glng[i] = acc;
 }
@@ -231,9 +242,12 @@ __global__ void __launch_bounds__(TILE) k_grid_cols(Geo geo, const double* beta,
         const double E = 4.0 * (geo.e0 + ie) - 2.0 * geo.N;
 #pragma unroll
         for (int k = 0; k < GB; ++k) {
-            const double w = exp((l - b[k] * E) - mx[k]);
-            s0[k] += w;
-            s1[k] += w * E;
+            const double d = (l - b[k] * E) - mx[k];
+            if (d > CUT) {
+                const double w = exp(d);
+                s0[k] += w;
+                s1[k] += w * E;
+            }
         }
     }
     if (u1) {
@@ -249,8 +263,11 @@ __global__ void __launch_bounds__(TILE) k_grid_cols(Geo geo, const double* beta,
             const double E = 4.0 * (geo.e0 + ie) - 2.0 * geo.N;
 #pragma unroll
             for (int k = 0; k < GB; ++k) {
-                const double d = E - mean[k];
-                s2[k] += exp((l - b[k] * E) - mx[k]) * d * d;
+                const double x = (l - b[k] * E) - mx[k];
+                if (x > CUT) {
+                    const double d = E - mean[k];
+                    s2[k] += exp(x) * d * d;
+                }
             }
         }
 #pragma unroll
@@ -290,7 +307,7 @@ __global__ void __launch_bounds__(TILE) k_grid_rows(const double* A, int N, int 
                 const double M = 2.0 * (m0 + base + q) - 1.0 * N;
                 const double x = sa[q] + bh * M;
                 if (pass == 0) mx = fmax(mx, x);
-                else if (sa[q] != -INFINITY) sum += exp(x - mx);
+                else if (x - mx > CUT) sum += exp(x - mx);
             }
         }
     }
@@ -328,7 +345,9 @@ __global__ void __launch_bounds__(TILE) k_grid_mom(const double* A, const double
             for (int q = 0; q < n; ++q) {
                 if (sa[q] == -INFINITY) continue;
                 const double M = 2.0 * (m0 + base + q) - 1.0 * N;
-                const double p = exp(sa[q] + bh * M - z);
+                const double dz = sa[q] + bh * M - z;
+                if (!(dz > CUT)) continue;
+                const double p = exp(dz);
                 const double ub = -s1[q] + h * M;
                 if (pass == 0) {
                     c0 += p;
@@ -404,7 +423,10 @@ __global__ void __launch_bounds__(TILE) k_grid_colw(const double* A, int N, int 
         __syncthreads();
         if (a == -INFINITY) continue;
         const int n = static_cast<int>(nH - base < TILE ? nH - base : TILE);
-        for (int q = 0; q < n; ++q) acc += sg[q] * exp(a + bM * sh[q] - sz[q]);
+        for (int q = 0; q < n; ++q) {
+            const double d = a + bM * sh[q] - sz[q];
+            if (d > CUT) acc += sg[q] * exp(d);
+        }
     }
     if (on) cw[i * nM + im] = acc;
 }
@@ -433,7 +455,8 @@ __global__ void __launch_bounds__(TILE) k_grid_glng(Geo geo, const double* beta,
         const int n = static_cast<int>(nB - base < TILE ? nB - base : TILE);
         for (int q = 0; q < n; ++q) {
             const int64_t o = (base + q) * geo.nM + im;
-            acc += exp(l - sb[q] * E - A[o]) * cw[o];
+            const double d = l - sb[q] * E - A[o];
+            if (d > CUT) acc += exp(d) * cw[o];
         }
     }
     if (idx < nb) glng[idx] = acc;

@@ -15,8 +15,11 @@ p8w2 / p8w20 = 8x8, 3 windows (overlap 1/2) x 2 or 20 walkers, ln f -> 2^-20;
 p8pair = 8x8 serial 2D-WL (one walker over the whole (E, M) space) next to
 8x8 2D-REWL (3 windows, overlap 1/2, 3 walkers), both to ln f = 2^-20, with
 the relative difference of Eq. 5 between the two joint densities of states
-(Sec. 3, Fig. 4(b)).  Replica r uses seed r (the serial runs of p8pair use
-seed 1000 + r).  Progress is printed every minute.
+(Sec. 3, Fig. 4(b)); p8sync = the same 8x8 REWL problem with all windows
+refining together (the paper) and with each window refining alone after
+averaging its walkers, compared in accuracy and in trials to finish.
+Replica r uses seed r (the second group uses seed 1000 + r).  Progress is
+printed every minute.
 """
 import argparse
 import json
@@ -37,6 +40,8 @@ CONFIGS = {
     "p8w2": [dict(P8, n_windows=3, walkers_per_window=2)],
     "p8w20": [dict(P8, n_windows=3, walkers_per_window=20)],
     "p8pair": [dict(P8, n_windows=3, walkers_per_window=3), dict(P8, n_windows=1, walkers_per_window=1)],
+    "p8sync": [dict(P8, n_windows=3, walkers_per_window=3),
+               dict(P8, n_windows=3, walkers_per_window=3, stage_sync=1)],
 }
 
 
@@ -116,7 +121,8 @@ def main():
     margs = {gi: [] for gi in range(len(groups))}
     joints = {}
     for i, (gi, r) in enumerate(tags):
-        out = {"group": gi, "replica": r}
+        qw = plan.query_windows(i)
+        out = {"group": gi, "replica": r, "window_trials_per_walker": [int(x) for x in qw["trials"]]}
         for norm in ("ground", "sum"):
             jt, g, em = plan.merge(i, norm)
             g = g.cpu().numpy()
@@ -141,7 +147,11 @@ def main():
         res["replica_mean"].append({"group": gi, "max_eps": float(eps_mean.max()), "mean_eps": float(eps_mean.mean()),
                                     "max_jackknife_err": float(err.max()),
                                     "max_abs_over_err": float(np.max(np.abs(mean - ex[ok]) / np.maximum(err, 1e-300)))})
-    if len(groups) == 2:
+    for gi in range(len(groups)):
+        tw = [sum(o["window_trials_per_walker"]) / len(o["window_trials_per_walker"])
+              for o in res["per_replica"] if o["group"] == gi]
+        res["replica_mean"][gi]["mean_trials_per_walker_to_finish"] = float(np.mean(tw))
+    if args.config == "p8pair":
         # Eq. 5 between the REWL (group 0) and serial WL (group 1) joint DOS of each replica pair
         diffs = []
         for r in range(args.replicas):

@@ -248,3 +248,29 @@ def test_mixed_sync_batch_bit_exact():
             o.run(25)
         for i, o in enumerate(orcs):
             compare(plan, i, o)
+
+
+def test_degenerate_sizes_bit_exact():
+    """k_final = 0 (one stage), an interval of one trial (every sweep starts or
+    ends in the middle of a Philox block), and 256 walkers per window."""
+    R = _R()
+    cases = [
+        ("K=0, X=7", R.Problem(L=4, n_windows=1, walkers_per_window=1, k_final=0, interval=7, seed=9), 5, 1),
+        ("X=1, per-window rule", R.Problem(L=6, n_windows=3, overlap=(1, 2), walkers_per_window=2, k_final=3,
+                                            interval=1, seed=4, stage_sync=R.SYNC_WINDOW), 3000, 500),
+        ("X=1, problem rule",
+         R.Problem(L=8, n_windows=2, walkers_per_window=3, k_final=4, interval=1, seed=6), 2000, 400),
+        ("256 walkers per window", R.Problem(L=4, n_windows=2, overlap=(1, 2), walkers_per_window=256, k_final=4,
+                                             interval=50, seed=5), 100, 25),
+    ]
+    for name, p, total, step in cases:
+        _say("case:", name)
+        plan = R.Plan([p], R.Tuning(graph_intervals=4))
+        plan.init()
+        orc = _oracle_of(p)
+        done = 0
+        while done < total:
+            plan.run(step)
+            orc.run(step)
+            done += step
+            compare(plan, 0, orc)

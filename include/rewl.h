@@ -23,8 +23,9 @@
  *     device pointers (any allocator; the Python binding uses PyTorch) and a
  *     hipStream_t.  The library never frees them; they must outlive the plan.
  *   - All device work is enqueued on the bound stream.  Only rewl_init,
- *     rewl_query, rewl_read_walker, rewl_merge_lng and rewl_sweep_times
- *     synchronise it.
+ *     rewl_query, rewl_query_windows, rewl_read_walker, rewl_merge_lng,
+ *     rewl_save, rewl_load and rewl_sweep_times synchronise it (and rewl_run
+ *     in the plain form, once per interval).
  *   - Arguments are validated before any device work (REWL_EINVAL).  A HIP
  *     error surfaces as REWL_EDEVICE; after it the plan answers REWL_ESTATE
  *     to every call but rewl_plan_destroy.

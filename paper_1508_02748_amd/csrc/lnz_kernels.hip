@@ -4,9 +4,10 @@
 //
 // One thread per grid point (beta, h); a workgroup of 256 grid points streams
 // the ln g table through LDS in chunks of 256 bins, so every bin is read from
-// HBM once per workgroup and broadcast to its 256 threads.  ln Z takes two
-// passes (maximum, then the shifted exponential sum); the moments pass reuses
-// the saved ln Z as the shift.  Unvisited bins hold -inf and contribute zero.
+// HBM once per workgroup and broadcast to its 256 threads.  ln Z takes one
+// pass (an exponential sum kept relative to the running maximum); the moments
+// pass reuses the saved ln Z as the shift.  Unvisited bins hold -inf and
+// contribute zero.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -46,7 +47,9 @@ __global__ void __launch_bounds__(TILE) k_lnz_fwd(Geo geo, const double* beta, c
     const double b = on ? beta[gp] : 0.0;
     const double bh = on ? b * hf[gp] : 0.0;
     const int64_t nb = static_cast<int64_t>(geo.nE) * geo.nM;
-    double mx = -INFINITY;
+    // one pass: the sum is kept relative to the largest term met so far and
+    // rescaled when a larger one appears
+    double mx = -INFINITY, sum = 0.0;
     for (int64_t base = 0; base < nb; base += TILE) {
         const int64_t i = base + threadIdx.x;
         double E = 0, M = 0, l = -INFINITY;
@@ -62,26 +65,13 @@ __global__ void __launch_bounds__(TILE) k_lnz_fwd(Geo geo, const double* beta, c
         const int n = static_cast<int>(nb - base < TILE ? nb - base : TILE);
         for (int j = 0; j < n; ++j) {
             const double x = sl[j] - b * sE[j] + bh * sM[j];
-            mx = fmax(mx, x);
-        }
-    }
-    double sum = 0.0;
-    for (int64_t base = 0; base < nb; base += TILE) {
-        const int64_t i = base + threadIdx.x;
-        double E = 0, M = 0, l = -INFINITY;
-        if (i < nb) {
-            l = geo.lng[i];
-            em_of(geo, i, E, M);
-        }
-        __syncthreads();
-        sl[threadIdx.x] = l;
-        sE[threadIdx.x] = E;
-        sM[threadIdx.x] = M;
-        __syncthreads();
-        const int n = static_cast<int>(nb - base < TILE ? nb - base : TILE);
-        for (int j = 0; j < n; ++j) {
-            const double d = (sl[j] - b * sE[j] + bh * sM[j]) - mx;
-            if (d > CUT) sum += exp(d);
+            if (x > mx) {
+                sum = (mx - x > CUT ? sum * exp(mx - x) : 0.0) + 1.0;
+                mx = x;
+            } else {
+                const double d = x - mx;
+                if (d > CUT) sum += exp(d);
+            }
         }
     }
     if (on) lnz[gp] = mx + log(sum);
@@ -391,13 +381,18 @@ __global__ void __launch_bounds__(TILE) k_grid_sum_rows(const double* tb, int64_
     gbeta[i] = s;
 }
 
-// grad_h(j) = sum_i th(i, j): one thread per h_j, coalesced over j.
+// grad_h(j) = sum_i th(i, j): a workgroup per 64 columns, its four waves
+// summing every fourth row, then the four partial sums in a fixed order.
 __global__ void __launch_bounds__(TILE) k_grid_sum_cols(const double* th, int64_t nB, int64_t nH, double* gh) {
-    const int64_t j = static_cast<int64_t>(blockIdx.x) * TILE + threadIdx.x;
-    if (j >= nH) return;
+    __shared__ double part[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 64 + lane;
     double s = 0.0;
-    for (int64_t i = 0; i < nB; ++i) s += th[i * nH + j];
-    gh[j] = s;
+    if (j < nH)
+        for (int64_t i = wave; i < nB; i += 4) s += th[i * nH + j];
+    part[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && j < nH) gh[j] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 // c(i, M) = sum_j grad_out(i, j) exp(A(i, M) + beta_i h_j M - ln Z(i, j)):
@@ -517,7 +512,8 @@ hipError_t launch_lnz_grid_backward(const double* lng, int N, int e0, int nE, in
                            m0, nM, beta, h, nH, lnz, gout, mom, tb, th);
     if (tb) {
         hipLaunchKernelGGL(k_grid_sum_rows, dim3(nblk(nB)), dim3(TILE), 0, st, tb, nB, nH, gbeta);
-        hipLaunchKernelGGL(k_grid_sum_cols, dim3(nblk(nH)), dim3(TILE), 0, st, th, nB, nH, gh);
+        hipLaunchKernelGGL(k_grid_sum_cols, dim3(static_cast<unsigned>((nH + 63) / 64)), dim3(TILE), 0, st, th, nB,
+                           nH, gh);
     }
     if (glng) {
         hipLaunchKernelGGL(k_grid_colw, dim3(nblk(nM), static_cast<unsigned>(nB)), dim3(TILE), 0, st, A, N, m0, nM,

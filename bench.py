@@ -152,8 +152,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "independent replicas or window blocks would shard across GPUs, but this build has "
-              "no multi-GPU path", file=sys.stderr)
+              "independent replicas or window blocks would shard across GPUs, but no multi-GPU path is "
+              "implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -6,7 +6,7 @@ problem's fragments on the device (Eq. 3, Eq. 4) and compares the marginal
 ln g(E) with the exact finite-lattice values stored in tests/golden/ (Sec. 3,
 Fig. 5):  epsilon(E) = |ln g - ln g_exact| / ln g_exact over realizable E.
 
-  python tests/long_convergence.py --config c2 --replicas 8 --seconds 900 --out gpurun_out/conv_c2
+  python tests/long_convergence.py --config c2 --replicas 8 --seconds 900 --out runs/conv_c2
   python tests/long_convergence.py --config c2 ... --resume      # continue from the checkpoint
   python tests/long_convergence.py --config c2 ... --resume --evaluate-now   # compare the state reached
 
@@ -61,7 +61,7 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--replicas", type=int, default=8)
     ap.add_argument("--seconds", type=float, default=900)
-    ap.add_argument("--out", default="gpurun_out/conv")
+    ap.add_argument("--out", default="runs/conv")
     ap.add_argument("--resume", action="store_true")
     ap.add_argument("--evaluate-now", action="store_true",
                     help="compare the current (unfinished) state with the exact g(E) instead of running on")

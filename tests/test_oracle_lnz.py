@@ -89,3 +89,33 @@ def test_grad_lng_is_the_probability_table():
     fd = (Z.lnz(lp, b, h)[0] - Z.lnz(lm, b, h)[0]) / (2 * d)
     _, _, g1 = Z.grads(lng, b, h)
     assert abs(fd - g1[i, j]) < 1e-7
+
+
+def _onsager(beta):
+    """Onsager's free energy of the infinite square lattice: lim ln Z / N at h = 0."""
+    import math
+    from scipy.integrate import quad
+    k = 2.0 * math.sinh(2.0 * beta) / math.cosh(2.0 * beta) ** 2
+    integ = quad(lambda p: math.log((1.0 + math.sqrt(max(0.0, 1.0 - (k * math.sin(p)) ** 2))) / 2.0),
+                 0.0, math.pi / 2.0, limit=200, epsabs=1e-14, epsrel=1e-14)[0]
+    return math.log(2.0 * math.cosh(2.0 * beta)) + integ / math.pi
+
+
+@pytest.mark.parametrize("L", [16, 32])
+def test_lnz_of_the_exact_tables_against_onsager(L):
+    """ln Z(beta, 0) / N of the stored exact g(E) (tests/golden; times the binomial in M) against
+    Onsager's infinite-lattice result: equal away from beta_c = 0.4407 up to
+    finite-size terms that are exponentially small in L, plus ln 2 / N in the
+    ordered phase (the finite lattice counts both ordered states)."""
+    import json
+    import math
+    import os
+    N = L * L
+    with open(os.path.join(os.path.dirname(__file__), "golden", "exact_lngE.json")) as f:
+        lge = np.array([-np.inf if v is None else v for v in json.load(f)["lattices"][str(L)]["lnge"]])
+    lng = lge[:, None] + exact.binomial_lng(N)[None, :] - N * math.log(2.0)
+    for beta, tol in ((0.1, 1e-12), (0.2, 1e-9), (0.3, 1e-6 if L == 16 else 1e-10)):
+        assert abs(float(Z.lnz(lng, beta, 0.0)[0]) / N - _onsager(beta)) < tol, (L, beta)
+    for beta in (0.6, 0.8, 1.0):
+        d = float(Z.lnz(lng, beta, 0.0)[0]) / N - _onsager(beta)
+        assert abs(d - math.log(2.0) / N) < 1e-9, (L, beta, d)

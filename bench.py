@@ -40,6 +40,50 @@ WORKLOADS = {
     "c4": (C4, 28, "64x64 periodic Ising 2D-REWL (64 windows x 4 walkers, overlap 3/4, ln f 1 -> 2^-20, "
                    "80% flat, exchange every 10^5 trials)"),
 }
+# Serial 2D-WL on the 4x4 lattice (one window, one walker), run to its last stage.
+C1 = dict(L=4, n_windows=1, overlap=(3, 4), walkers_per_window=1, k_final=16, flat=(4, 5), interval=10_000)
+
+
+def full_run(R, torch, replicas):
+    """Whole runs to the final ln f (Sec. 2): the 4x4 serial 2D-WL problem once in the plain form,
+    once in the batched form (same final state), and `replicas` independent copies in one batched
+    plan; trials per second from the first sweep to the boundary where the last problem ends."""
+    def to_end(plan, chunk):
+        plan.stream.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            plan.run(chunk)
+            n += chunk
+            q = plan.query()
+            if q["done"].all():
+                break
+        return time.perf_counter() - t0, n, q
+    out = {"workload": "4x4 periodic Ising serial 2D-WL (1 window x 1 walker, ln f 1 -> 2^-16, 80% flat, "
+                       "flatness check every 10^4 trials), run to the end"}
+    one = problems(1, R, C1)
+    pp = R.Plan(one, R.Tuning(form=R.FORM_PLAIN))
+    pp.init()
+    Tp, _, qp = to_end(pp, 16)
+    pb = R.Plan(one, R.Tuning(graph_intervals=16))
+    pb.init()
+    Tb, _, qb = to_end(pb, 16)
+    same = bool((pp.walker(0, 0, 0)["lng"] == pb.walker(0, 0, 0)["lng"]).all())
+    trials1 = int(qp["trials"][0])
+    out.update({"one_problem_trials": trials1, "plain_s": Tp, "batched_s": Tb, "plain_value": trials1 / Tp,
+                "batched_value": trials1 / Tb, "identical_final_state": same})
+    del pp, pb
+    plan = R.Plan(problems(replicas, R, C1), R.Tuning(graph_intervals=16))
+    plan.init()
+    T, n, q = to_end(plan, 256)
+    total = int(q["trials"].sum())
+    out.update({"replicas": replicas, "batch_s": T, "batch_intervals": n, "batch_trials": total,
+                "batch_value": total / T, "unit": "spin-flip attempts/s",
+                "trials_per_problem_min_max": [int(q["trials"].min()), int(q["trials"].max())]})
+    return out
+
+
 # Algorithmic VALU issue slots per trial (full-rate 32-bit lane operations; a
 # 32x32->64 multiply counts 4): derivation in the design notes.
 VALU_SLOTS_PER_TRIAL = 133
@@ -138,6 +182,8 @@ def main():
     ap.add_argument("--no-lnz", action="store_true")
     ap.add_argument("--wg", type=int, default=0, help="walkers per workgroup (0 = library's choice)")
     ap.add_argument("--grid-waves", type=int, default=0, help="persistent grid waves per CU (0 = library's choice)")
+    ap.add_argument("--full-run", type=int, default=0, metavar="R",
+                    help="only run the 4x4 serial problem to its end: plain, batched, and R replicas batched")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -159,6 +205,10 @@ def main():
     import numpy as np
     import torch
     import paper_1508_02748_amd as R
+
+    if args.full_run:
+        print(json.dumps(full_run(R, torch, args.full_run)), flush=True)
+        return
 
     dev = "cuda:0"
     K, W = args.steps, args.warmup

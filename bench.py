@@ -90,9 +90,10 @@ VALU_SLOTS_PER_TRIAL = 133
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz full-rate VALU lane operations per second.
 VALU_PEAK_SLOTS = 256 * 64 * 2.4e9
 # HBM-side bytes per sweep launch, FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a 1 GiB
-# device copy), by (workload, replicas, walkers per workgroup, grid waves per CU); measured on
+# device copy), by (workload, replicas, walkers per workgroup, grid waves per CU, walkers per
+# wavefront); measured on
 # the current sweep kernel with rocprofv3 --pmc.  Other shapes report null.
-TRAFFIC_BYTES = {("c2", 4096, 256, 4): 38.44e9}
+TRAFFIC_BYTES = {("c2", 4096, 256, 4, 0): 38.44e9}
 
 
 def log(*a):
@@ -226,12 +227,13 @@ def main():
     plan.init()
     log(f"[bench] init + window entry {time.perf_counter() - t0:.2f}s; warmup {W}, timed {K} steps")
     tuned = "fixed"
-    shape = (args.wg, args.grid_waves)
+    shape = (args.wg, args.grid_waves, 0)
     if not args.no_autotune and args.wg == 0 and args.grid_waves == 0:
         from paper_1508_02748_amd.tune import autotune
         best = autotune(plan, intervals=1, use_cache=False)
-        shape = (best.walkers_per_wg, best.grid_waves_per_cu)
-        tuned = f"autotuned: walkers_per_wg={best.walkers_per_wg}, grid_waves_per_cu={best.grid_waves_per_cu}"
+        shape = (best.walkers_per_wg, best.grid_waves_per_cu, best.walkers_per_wave)
+        tuned = (f"autotuned: walkers_per_wg={best.walkers_per_wg}, grid_waves_per_cu={best.grid_waves_per_cu}, "
+                 f"walkers_per_wave={best.walkers_per_wave or 64}")
         log(f"[bench] {tuned}")
     traffic = TRAFFIC_BYTES.get((args.workload, args.replicas) + shape)
     # timed region: the batched launch sequence enqueued eagerly with a HIP

@@ -97,12 +97,15 @@ typedef struct {
     int32_t grid_waves_per_cu;/* persistent grid: at most this many wavefronts per CU, each
                                  running its tiles of walkers in turn; 0 = auto */
     int32_t profile;          /* 1: start with profiling on (see rewl_set_profile) */
-    int32_t reserved[3];      /* must be 0 */
+    int32_t walkers_per_wave; /* 1..64 lanes of each wavefront carry a walker; fewer spread
+                                 a small batch over more CUs; 0 = 64 */
+    int32_t reserved[2];      /* must be 0 */
 } rewl_tuning;
 
 /* Buffers the caller provides (device memory). */
 enum {
-    REWL_BUF_TABLES = 0,  /* ln g / H tables: 16 B per (walker, e in window, m) bin */
+    REWL_BUF_TABLES = 0,  /* ln g and its stage snapshot: 2 x 8 B per bin of each walker's
+                             window table (4 x 4 tiles of (e, m)) */
     REWL_BUF_SPINS = 1,   /* bit-packed configurations */
     REWL_BUF_STATE = 2,   /* descriptors, walker and problem state, scratch */
     REWL_NBUF = 3

@@ -42,7 +42,8 @@ class _Problem(C.Structure):
 
 class _Tuning(C.Structure):
     _fields_ = [("form", C.c_int32), ("walkers_per_wg", C.c_int32), ("graph_intervals", C.c_int32),
-                ("grid_waves_per_cu", C.c_int32), ("profile", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("grid_waves_per_cu", C.c_int32), ("profile", C.c_int32), ("walkers_per_wave", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 _lib = None
@@ -139,10 +140,11 @@ class Tuning:
     graph_intervals: int = 0
     grid_waves_per_cu: int = 0
     profile: int = 0
+    walkers_per_wave: int = 0
 
     def _c(self):
         return _Tuning(self.form, self.walkers_per_wg, self.graph_intervals, self.grid_waves_per_cu,
-                       self.profile, (C.c_int32 * 3)(0, 0, 0))
+                       self.profile, self.walkers_per_wave, (C.c_int32 * 2)(0, 0))
 
 
 class Plan:

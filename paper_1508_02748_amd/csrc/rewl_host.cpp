@@ -123,6 +123,7 @@ rewl_status validate_tuning(const rewl_tuning& tn) {
     if (tn.graph_intervals < 0 || tn.graph_intervals > 4096) return fail(REWL_EINVAL, "graph_intervals 0..4096");
     if (tn.grid_waves_per_cu < 0 || tn.grid_waves_per_cu > 64) return fail(REWL_EINVAL, "grid_waves_per_cu 0..64");
     if (tn.profile != 0 && tn.profile != 1) return fail(REWL_EINVAL, "profile must be 0 or 1");
+    if (tn.walkers_per_wave < 0 || tn.walkers_per_wave > 64) return fail(REWL_EINVAL, "walkers_per_wave 0..64");
     if (tn.profile && tn.form != REWL_FORM_BATCHED) return fail(REWL_EINVAL, "profiling times the batched form");
     for (int r : tn.reserved)
         if (r != 0) return fail(REWL_EINVAL, "tuning.reserved must be 0");
@@ -189,7 +190,8 @@ int max_grid_of(const rewl_plan* P) {
 
 rewl_status enqueue_sweep(rewl_plan* P, int64_t n, int ev_slot = -1) {
     if (ev_slot >= 0) HIPCHK(P, hipEventRecord(P->ev[2 * ev_slot], P->stream), "event record");
-    HIPCHK(P, launch_sweep(P->S, 0, P->n_walk, n, P->l_max, wg_of(P), max_grid_of(P), P->stream), "sweep launch");
+    HIPCHK(P, launch_sweep(P->S, 0, P->n_walk, n, P->l_max, wg_of(P), max_grid_of(P), P->tune.walkers_per_wave,
+                           P->stream), "sweep launch");
     if (ev_slot >= 0) HIPCHK(P, hipEventRecord(P->ev[2 * ev_slot + 1], P->stream), "event record");
     return REWL_OK;
 }
@@ -241,7 +243,7 @@ rewl_status run_interval_plain(rewl_plan* P) {
         const PDesc& q = P->pd[p];
         for (int w = 0; w < q.nwin; ++w) {
             HIPCHK(P, launch_sweep(P->S, q.walker_off + static_cast<int64_t>(w) * q.W, q.W, P->interval,
-                                   q.L, wg, 0, P->stream), "plain sweep launch");
+                                   q.L, wg, 0, P->tune.walkers_per_wave, P->stream), "plain sweep launch");
         }
     }
     HIPCHK(P, launch_flat(P->S, P->stream), "flatness launch");
@@ -601,7 +603,7 @@ rewl_status rewl_sweep(rewl_plan* P, int64_t n) {
         for (const PDesc& q : P->pd)
             for (int w = 0; w < q.nwin; ++w)
                 HIPCHK(P, launch_sweep(P->S, q.walker_off + static_cast<int64_t>(w) * q.W, q.W, n, q.L, wg, 0,
-                                       P->stream), "plain sweep launch");
+                                       P->tune.walkers_per_wave, P->stream), "plain sweep launch");
         return REWL_OK;
     }
     return enqueue_sweep(P, n);

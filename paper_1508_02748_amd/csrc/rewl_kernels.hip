@@ -422,15 +422,19 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
 // same XCD.
 template <typename RowT>
 __global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int64_t g_count,
-                                               int64_t n_trials) {
+                                               int64_t n_trials, int wpw) {
     extern __shared__ unsigned char lds_raw[];
     RowT* lds = reinterpret_cast<RowT*>(lds_raw);
     const int lane = threadIdx.x;
     const int WG = blockDim.x;
-    const int64_t n_tiles = (g_count + WG - 1) / WG;
+    // the first wpw lanes of each wavefront carry a walker (fewer than 64 spread
+    // a small batch over more CUs, so each walker has more of an L1 to itself)
+    const int wave = lane >> 6, wl = lane & 63;
+    const int per = (WG >> 6) * wpw;
+    const int64_t n_tiles = (g_count + per - 1) / per;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t gi = tile * WG + lane;
-        if (gi < g_count) sweep_walker<RowT>(S, lds, lane, WG, g_begin + gi, n_trials);
+        const int64_t gi = tile * per + wave * wpw + wl;
+        if (wl < wpw && gi < g_count) sweep_walker<RowT>(S, lds, lane, WG, g_begin + gi, n_trials);
     }
 }
 
@@ -733,16 +737,17 @@ hipError_t launch_entry(const DevState& S, int64_t cap, hipStream_t st) {
 }
 
 hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int64_t n_trials,
-                        int l_max, int wg, int max_grid, hipStream_t st) {
+                        int l_max, int wg, int max_grid, int wpw, hipStream_t st) {
     if (g_count <= 0 || n_trials <= 0) return hipSuccess;
-    int grid = blocks_for(g_count, wg);
+    if (wpw <= 0 || wpw > 64) wpw = 64;
+    int grid = blocks_for(g_count, (wg / 64) * wpw);
     if (max_grid > 0 && grid > max_grid) grid = max_grid;
     if (l_max <= 32) {
         const size_t lds = static_cast<size_t>(l_max) * wg * sizeof(uint32_t);
-        hipLaunchKernelGGL(k_sweep<uint32_t>, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials);
+        hipLaunchKernelGGL(k_sweep<uint32_t>, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
     } else {
         const size_t lds = static_cast<size_t>(l_max) * wg * sizeof(uint64_t);
-        hipLaunchKernelGGL(k_sweep<uint64_t>, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials);
+        hipLaunchKernelGGL(k_sweep<uint64_t>, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
     }
     return hipGetLastError();
 }

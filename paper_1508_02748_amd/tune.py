@@ -1,4 +1,5 @@
-"""Autotuner for the batched sweep: walkers per workgroup and persistent-grid size.
+"""Autotuner for the batched sweep: walkers per workgroup, persistent-grid size and,
+for batches smaller than one wavefront per CU, walkers per wavefront.
 
 The launch shape changes neither the trajectory nor the tables (every random
 number is addressed by walker and trial index), so candidates can be timed on
@@ -16,6 +17,9 @@ from . import FORM_BATCHED, Tuning
 
 WG_CANDIDATES = (64, 128, 256)
 GRID_CANDIDATES = (2, 3, 4, 5, 6, 8)
+# a small batch can spread its walkers over more CUs (fewer lanes per wavefront)
+WAVE_CANDIDATES = (32, 16, 8, 4, 2, 1)
+SMALL_BATCH = 64 * 256
 
 
 def _cache_path():
@@ -56,37 +60,41 @@ def autotune(plan, intervals=1, candidates=None, use_cache=True, verbose=False):
         hit = _load_cache(path).get(key)
         if hit:
             best = Tuning(form=FORM_BATCHED, walkers_per_wg=hit["wg"], graph_intervals=base.graph_intervals,
-                          grid_waves_per_cu=hit["gw"])
+                          grid_waves_per_cu=hit["gw"], walkers_per_wave=hit.get("wpw", 0))
             plan.set_tuning(best)
             return best
     if candidates is None:
-        candidates = [(wg, gw) for wg in WG_CANDIDATES for gw in GRID_CANDIDATES]
+        candidates = [(wg, gw, 0) for wg in WG_CANDIDATES for gw in GRID_CANDIDATES]
+        if plan.n_walkers < SMALL_BATCH:
+            candidates += [(64, 0, wpw) for wpw in WAVE_CANDIDATES]
+    candidates = [c if len(c) == 3 else (c[0], c[1], 0) for c in candidates]
     plan.stream.synchronize()
     saved = [b.clone() for b in plan.buffers]
     torch.cuda.synchronize(plan.device)
     results = []
     try:
-        for wg, gw in candidates:
+        for wg, gw, wpw in candidates:
             t = Tuning(form=FORM_BATCHED, walkers_per_wg=wg, graph_intervals=base.graph_intervals,
-                       grid_waves_per_cu=gw, profile=1)
+                       grid_waves_per_cu=gw, profile=1, walkers_per_wave=wpw)
             plan.set_tuning(t)
             plan.run(intervals)
             ms = float(plan.sweep_times().mean())
-            results.append((ms, wg, gw))
+            results.append((ms, wg, gw, wpw))
             if verbose:
-                print(f"[tune] wg={wg} grid_waves_per_cu={gw}: {ms:.3f} ms", flush=True)
+                print(f"[tune] wg={wg} grid_waves_per_cu={gw} walkers_per_wave={wpw}: {ms:.3f} ms", flush=True)
             with torch.cuda.stream(plan.stream):
                 for b, s in zip(plan.buffers, saved):
                     b.copy_(s)
             plan.stream.synchronize()
     finally:
         del saved
-    ms, wg, gw = min(results)
-    best = Tuning(form=FORM_BATCHED, walkers_per_wg=wg, graph_intervals=base.graph_intervals, grid_waves_per_cu=gw)
+    ms, wg, gw, wpw = min(results)
+    best = Tuning(form=FORM_BATCHED, walkers_per_wg=wg, graph_intervals=base.graph_intervals, grid_waves_per_cu=gw,
+                  walkers_per_wave=wpw)
     plan.set_tuning(best)
     if use_cache:
         cache = _load_cache(path)
-        cache[key] = {"wg": wg, "gw": gw, "sweep_ms": ms}
+        cache[key] = {"wg": wg, "gw": gw, "wpw": wpw, "sweep_ms": ms}
         os.makedirs(os.path.dirname(path), exist_ok=True)
         with open(path, "w") as f:
             json.dump(cache, f, indent=1)

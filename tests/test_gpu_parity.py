@@ -274,3 +274,23 @@ def test_degenerate_sizes_bit_exact():
             orc.run(step)
             done += step
             compare(plan, 0, orc)
+
+
+def test_walkers_per_wave_shapes_bit_exact():
+    """Fewer walkers per wavefront (a small batch spread over more CUs) and any
+    workgroup size give the same trajectories."""
+    R = _R()
+    probs = [R.Problem(L=8, n_windows=3, walkers_per_window=5, k_final=8, interval=700, seed=40),
+             R.Problem(L=12, n_windows=2, walkers_per_window=7, k_final=8, interval=700, seed=41)]
+    orcs = [_oracle_of(p) for p in probs]
+    for o in orcs:
+        o.run(12)
+    for wg, wpw in ((64, 1), (64, 5), (128, 37), (256, 3), (256, 64)):
+        _say("case: walkers_per_wg", wg, "walkers_per_wave", wpw)
+        for form in (R.FORM_BATCHED, R.FORM_PLAIN):
+            plan = R.Plan(probs, R.Tuning(form=form, walkers_per_wg=wg, walkers_per_wave=wpw,
+                                          graph_intervals=3 if form == R.FORM_BATCHED else 0))
+            plan.init()
+            plan.run(12)
+            for i, o in enumerate(orcs):
+                compare(plan, i, o)

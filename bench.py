@@ -93,7 +93,7 @@ VALU_PEAK_SLOTS = 256 * 64 * 2.4e9
 # device copy), by (workload, replicas, walkers per workgroup, grid waves per CU, walkers per
 # wavefront); measured on
 # the current sweep kernel with rocprofv3 --pmc.  Other shapes report null.
-TRAFFIC_BYTES = {}
+TRAFFIC_BYTES = {("c2", 4096, 256, 4, 0): 38.44e9}
 
 
 def log(*a):

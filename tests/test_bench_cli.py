@@ -1,0 +1,14 @@
+"""bench.py's command line on the CPU: more than one GPU is refused with a
+message, and the module parses (no GPU work)."""
+import os
+import subprocess
+import sys
+
+from tests.conftest import ROOT
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr

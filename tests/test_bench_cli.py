@@ -1,5 +1,5 @@
 """bench.py's command line on the CPU: more than one GPU is refused with a
-message, and the module parses (no GPU work)."""
+message before any GPU work."""
 import os
 import subprocess
 import sys

@@ -13,7 +13,7 @@ overlapping energy windows with configuration exchange (Eq. 1, Eq. 2).
 """
 import ctypes as C
 import os
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 

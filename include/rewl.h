@@ -26,6 +26,9 @@
  *     rewl_query, rewl_query_windows, rewl_read_walker, rewl_merge_lng,
  *     rewl_save, rewl_load and rewl_sweep_times synchronise it (and rewl_run
  *     in the plain form, once per interval).
+ *   - A plan is not internally synchronised: call it from one host thread at
+ *     a time.  Different plans are independent.  The reweighting calls keep
+ *     no state.
  *   - Arguments are validated before any device work (REWL_EINVAL).  A HIP
  *     error surfaces as REWL_EDEVICE; after it the plan answers REWL_ESTATE
  *     to every call but rewl_plan_destroy.

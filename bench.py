@@ -32,13 +32,20 @@ METRIC = "spin-flip attempts/sec on 1 MI355X (batched vs plain) at equal final l
 C2 = dict(L=16, n_windows=8, overlap=(3, 4), walkers_per_window=4, k_final=20, flat=(4, 5), interval=10_000)
 C3 = dict(L=32, n_windows=16, overlap=(3, 4), walkers_per_window=8, k_final=24, flat=(4, 5), interval=10_000)
 C4 = dict(L=64, n_windows=64, overlap=(3, 4), walkers_per_window=4, k_final=20, flat=(4, 5), interval=100_000)
+# A mixed batch of lattice sizes with uneven window counts, run in the same
+# launches as the 32x32 problems.
+MIXED = [dict(C3, L=L, n_windows=nw) for L, nw in ((8, 2), (12, 4), (16, 8), (24, 12), (32, 16))]
+# name -> (problems of one replica, default replica count, description)
 WORKLOADS = {
-    "c2": (C2, 4096, "16x16 periodic Ising 2D-REWL (8 windows x 4 walkers, overlap 3/4, ln f 1 -> 2^-20, "
-                     "80% flat, exchange every 10^4 trials)"),
-    "c3": (C3, 240, "32x32 periodic Ising 2D-REWL (16 windows x 8 walkers, overlap 3/4, ln f 1 -> 2^-24, "
-                    "80% flat, exchange every 10^4 trials)"),
-    "c4": (C4, 28, "64x64 periodic Ising 2D-REWL (64 windows x 4 walkers, overlap 3/4, ln f 1 -> 2^-20, "
-                   "80% flat, exchange every 10^5 trials)"),
+    "c2": ([C2], 4096, "16x16 periodic Ising 2D-REWL (8 windows x 4 walkers, overlap 3/4, ln f 1 -> 2^-20, "
+                       "80% flat, exchange every 10^4 trials)"),
+    "c3": ([C3], 240, "32x32 periodic Ising 2D-REWL (16 windows x 8 walkers, overlap 3/4, ln f 1 -> 2^-24, "
+                      "80% flat, exchange every 10^4 trials)"),
+    "c3mix": ([C3] + MIXED, 100, "32x32 periodic Ising 2D-REWL (16 windows x 8 walkers, overlap 3/4, ln f 1 -> "
+                                 "2^-24, 80% flat, exchange every 10^4 trials) plus a mixed batch of L in "
+                                 "{8,12,16,24,32} with 2/4/8/12/16 windows x 8 walkers, all in the same launches"),
+    "c4": ([C4], 28, "64x64 periodic Ising 2D-REWL (64 windows x 4 walkers, overlap 3/4, ln f 1 -> 2^-20, "
+                     "80% flat, exchange every 10^5 trials)"),
 }
 # Serial 2D-WL on the 4x4 lattice (one window, one walker), run to its last stage.
 C1 = dict(L=4, n_windows=1, overlap=(3, 4), walkers_per_window=1, k_final=16, flat=(4, 5), interval=10_000)
@@ -101,7 +108,9 @@ def log(*a):
 
 
 def problems(R, R_mod, cfg=C2):
-    return [R_mod.Problem(seed=s, **cfg) for s in range(R)]
+    """R replicas; cfg is one problem or a list of problems making up one replica (seed = running index)."""
+    cfgs = cfg if isinstance(cfg, list) else [cfg]
+    return [R_mod.Problem(seed=r * len(cfgs) + j, **c) for r in range(R) for j, c in enumerate(cfgs)]
 
 
 def time_plan(R, plan, steps, warmup):
@@ -174,7 +183,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--replicas", type=int, default=0, help="independent problems (0 = the workload's default)")
+    ap.add_argument("--replicas", type=int, default=0, help="independent replicas of the workload's problem set (0 = its default)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--cpu-intervals", type=int, default=1000)
@@ -213,16 +222,17 @@ def main():
 
     dev = "cuda:0"
     K, W = args.steps, args.warmup
-    cfg, default_r, wl_text = WORKLOADS[args.workload]
+    unit, default_r, wl_text = WORKLOADS[args.workload]
+    cfg = unit[0]
     if args.replicas <= 0:
         args.replicas = default_r
     X = cfg["interval"]
     n1 = cfg["n_windows"] * cfg["walkers_per_window"]
 
     # ---------------- batched form on the replica batch (the headline value)
-    log(f"[bench] batched: {args.replicas} replicas of the {cfg['L']}x{cfg['L']} REWL problem, init ...")
+    log(f"[bench] batched: {args.replicas} replicas of {len(unit)} REWL problem(s) ({args.workload}), init ...")
     tuning = R.Tuning(graph_intervals=K, walkers_per_wg=args.wg, grid_waves_per_cu=args.grid_waves)
-    plan = R.Plan(problems(args.replicas, R, cfg), tuning, device=dev)
+    plan = R.Plan(problems(args.replicas, R, unit), tuning, device=dev)
     t0 = time.perf_counter()
     plan.init()
     log(f"[bench] init + window entry {time.perf_counter() - t0:.2f}s; warmup {W}, timed {K} steps")
@@ -247,7 +257,7 @@ def main():
     q1 = plan.query()
     n_walk = plan.n_walkers
     active = int((~q1["done"]).sum())
-    assert active == args.replicas, "a replica finished during the timed region"
+    assert active == args.replicas * len(unit), "a replica finished during the timed region"
     trials = n_walk * X * K
     value = trials / T
     assert len(sweep_ms) == K

@@ -12,3 +12,18 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_mixed_workload_problem_list():
+    sys.path.insert(0, ROOT)
+    import bench
+    import paper_1508_02748_amd as R
+    unit = bench.WORKLOADS["c3mix"][0]
+    probs = bench.problems(3, R, unit)
+    assert len(probs) == 3 * 6
+    assert sorted({p.seed for p in probs}) == list(range(18))
+    assert [p.L for p in probs[:6]] == [32, 8, 12, 16, 24, 32]
+    assert [p.n_windows for p in probs[:6]] == [16, 2, 4, 8, 12, 16]
+    assert {p.interval for p in probs} == {10_000}
+    # one-problem workloads keep seed = replica index
+    assert [p.seed for p in bench.problems(4, R, bench.C2)] == [0, 1, 2, 3]

@@ -115,6 +115,8 @@ def main():
     L = groups[0]["L"]
     ex = exact_lnge(L)
     ok = np.isfinite(ex) & (ex > 0)
+    E_of = 4 * np.arange(ex.size)[ok] - 2 * L * L        # energies of the compared bins
+    inner = np.abs(E_of) < 2 * L * L                     # all but the two edge states E = -2N, +2N
     res = {"config": args.config,
            "problems": [{k: list(v) if isinstance(v, tuple) else v for k, v in c.items()} for c in groups],
            "replicas": args.replicas, **meta, "per_replica": []}
@@ -128,7 +130,9 @@ def main():
             g = g.cpu().numpy()
             eps = np.abs(g[ok] - ex[ok]) / ex[ok]
             out[norm] = {"max_eps": float(eps.max()), "mean_eps": float(eps.mean()),
-                         "max_abs": float(np.max(np.abs(g[ok] - ex[ok]))), "e_mat": em}
+                         "max_abs": float(np.max(np.abs(g[ok] - ex[ok]))), "e_mat": em,
+                         "E_of_max_eps": int(E_of[int(np.argmax(eps))]),
+                         "max_eps_without_edges": float(eps[inner].max())}
             if norm == "sum":
                 margs[gi].append(g)
                 joints[(gi, r)] = jt.cpu().numpy()
@@ -145,6 +149,7 @@ def main():
         err = np.sqrt((n - 1) / n * ((jk - jk.mean(0)) ** 2).sum(0))
         eps_mean = np.abs(mean - ex[ok]) / ex[ok]
         res["replica_mean"].append({"group": gi, "max_eps": float(eps_mean.max()), "mean_eps": float(eps_mean.mean()),
+                                    "max_eps_without_edges": float(eps_mean[inner].max()),
                                     "max_jackknife_err": float(err.max()),
                                     "max_abs_over_err": float(np.max(np.abs(mean - ex[ok]) / np.maximum(err, 1e-300)))})
     for gi in range(len(groups)):

@@ -307,8 +307,14 @@ def main():
         t0 = time.perf_counter()
         o.run(n)
         Tc = time.perf_counter() - t0
+        model = "unknown"
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next(ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
         cpu = {"value": n1 * X * n / Tc, "unit": "spin-flip attempts/s", "cores": min(threads, n1),
-               "kind": "oracle",
+               "kind": "oracle", "host_cpu": model,
                "sample": f"{n} intervals ({X} trials x {n1} walkers each) of one {cfg['L']}x{cfg['L']} REWL "
                          f"problem, seed 0; {Tc:.1f} s"}
 

@@ -336,6 +336,8 @@ def main():
                      "unit": "Tslot/s (full-rate VALU lane-ops)", "frac": achieved_slots / VALU_PEAK_SLOTS,
                      "traffic": traffic, "traffic_unit": "HBM bytes per sweep launch (rocprofv3 FETCH_SIZE, WRITE_SIZE)",
                      "kernel": "k_sweep", "kernel_ms": sweep_avg,
+                     "kernel_ms_source": "HIP events around each sweep launch in the eager pass (the graph "
+                                         "replay runs the kernel faster: ms_per_step can be below kernel_ms)",
                      "slots_per_trial": VALU_SLOTS_PER_TRIAL},
         "cpu_baseline": cpu,
         "plain": plain,

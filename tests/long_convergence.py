@@ -132,7 +132,11 @@ def main():
             out[norm] = {"max_eps": float(eps.max()), "mean_eps": float(eps.mean()),
                          "max_abs": float(np.max(np.abs(g[ok] - ex[ok]))), "e_mat": em,
                          "E_of_max_eps": int(E_of[int(np.argmax(eps))]),
-                         "max_eps_without_edges": float(eps[inner].max())}
+                         "max_eps_without_edges": float(eps[inner].max()),
+                         # signed ln g - ln g_exact at the three lowest and three highest energies
+                         "signed_err_ends": {int(E): float(v) for E, v in
+                                             zip(np.r_[E_of[:3], E_of[-3:]], np.r_[(g[ok] - ex[ok])[:3],
+                                                                                  (g[ok] - ex[ok])[-3:]])}}
             if norm == "sum":
                 margs[gi].append(g)
                 joints[(gi, r)] = jt.cpu().numpy()

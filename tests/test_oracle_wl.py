@@ -225,6 +225,27 @@ def test_c1_full_run_against_enumeration():
     assert (~np.isfinite(joint[~mask])).all()
 
 
+def test_c1_mean_over_100_runs_against_enumeration():
+    # Averaging 100 independent runs (seeds 0-99) shrinks the statistical error of one run
+    # (up to ~0.12 in a bin) tenfold; what stays is the method's residual bias at this ln f,
+    # measured at a few 10^-3 (0.008-0.012 worst bin over 200-seed blocks of seeds 0-999).
+    # A mistake that tilts the stationary distribution of Eq. (1), in the update or in the
+    # merge, shows up here at well below the single-run tolerance: accepting with 0.99 times
+    # the Eq. (1) ratio gives max 0.056 / rms 0.022 here but passes the single-run test.
+    G = exact.enumerate_joint(4)
+    mask = G > 0
+    acc = np.zeros(int(mask.sum()))
+    for seed in range(100):
+        o = OracleREWL(4, 1, (3, 4), 1, 16, (4, 5), 10_000, seed=seed)
+        o.init()
+        o.run_to_end()
+        joint, _, _ = MG.merge_oracle_run(o, "sum")
+        acc += joint[mask] - np.log(G[mask])
+    mean = acc / 100
+    assert np.abs(mean).max() < 0.035, np.abs(mean).max()
+    assert np.sqrt((mean ** 2).mean()) < 0.01
+
+
 @pytest.mark.slow
 def test_rewl_8x8_marginal_against_exact():
     ex = exact.exact_lngE(8)

@@ -2,12 +2,13 @@
 // ln Z(beta, h) = log sum_{(E,M)} exp(ln g(E,M) - beta E + beta h M) and its
 // derivatives, in float64 on gfx950.
 //
-// One thread per grid point (beta, h); a workgroup of 256 grid points streams
-// the ln g table through LDS in chunks of 256 bins, so every bin is read from
-// HBM once per workgroup and broadcast to its 256 threads.  ln Z takes one
-// pass (an exponential sum kept relative to the running maximum); the moments
-// pass reuses the saved ln Z as the shift.  Unvisited bins hold -inf and
-// contribute zero.
+// One thread per grid point (beta, h).  ln Z takes one pass over the bins (an
+// exponential sum kept relative to the running maximum), reading them through
+// scalar loads since every lane of a wavefront walks the same bins.  The
+// moment and d/d ln g kernels stream the table through LDS in chunks of 256
+// bins, each bin read once per workgroup and broadcast to its 256 threads, and
+// reuse the saved ln Z as the shift.  Unvisited bins hold -inf and contribute
+// zero.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -39,39 +40,50 @@ __device__ __forceinline__ void em_of(const Geo& g, int64_t i, double& E, double
     M = 2.0 * (g.m0 + im) - 1.0 * g.N;
 }
 
-__global__ void __launch_bounds__(TILE) k_lnz_fwd(Geo geo, const double* beta, const double* hf, int64_t G,
-                                                   double* lnz) {
-    __shared__ double sl[TILE], sE[TILE], sM[TILE];
+// One term of the one-pass sum: the sum is kept relative to the largest term
+// met so far and rescaled when a larger one appears.
+__device__ __forceinline__ void lse_step(double x, double& mx, double& sum) {
+    if (x > mx) {
+        sum = (mx - x > CUT ? sum * exp(mx - x) : 0.0) + 1.0;
+        mx = x;
+    } else {
+        const double d = x - mx;
+        if (d > CUT) sum += exp(d);
+    }
+}
+
+__global__ void __launch_bounds__(TILE) k_lnz_fwd(Geo geo, const double* __restrict__ beta,
+                                                   const double* __restrict__ hf, int64_t G,
+                                                   double* __restrict__ lnz) {
     const int64_t gp = static_cast<int64_t>(blockIdx.x) * TILE + threadIdx.x;
     const bool on = gp < G;
     const double b = on ? beta[gp] : 0.0;
     const double bh = on ? b * hf[gp] : 0.0;
-    const int64_t nb = static_cast<int64_t>(geo.nE) * geo.nM;
-    // one pass: the sum is kept relative to the largest term met so far and
-    // rescaled when a larger one appears
+    // Every lane walks the same bins in the same order, so the bin values are
+    // uniform across the wavefront: they come through scalar loads, eight at a
+    // time, and E, M are exact integer-valued doubles stepped per bin.  Only
+    // the per-point arithmetic runs on the vector unit.
+    const double* __restrict__ lg = geo.lng;
+    const int nM = geo.nM;
     double mx = -INFINITY, sum = 0.0;
-    for (int64_t base = 0; base < nb; base += TILE) {
-        const int64_t i = base + threadIdx.x;
-        double E = 0, M = 0, l = -INFINITY;
-        if (i < nb) {
-            l = geo.lng[i];
-            em_of(geo, i, E, M);
-        }
-        __syncthreads();
-        sl[threadIdx.x] = l;
-        sE[threadIdx.x] = E;
-        sM[threadIdx.x] = M;
-        __syncthreads();
-        const int n = static_cast<int>(nb - base < TILE ? nb - base : TILE);
-        for (int j = 0; j < n; ++j) {
-            const double x = sl[j] - b * sE[j] + bh * sM[j];
-            if (x > mx) {
-                sum = (mx - x > CUT ? sum * exp(mx - x) : 0.0) + 1.0;
-                mx = x;
-            } else {
-                const double d = x - mx;
-                if (d > CUT) sum += exp(d);
+    for (int ie = 0; ie < geo.nE; ++ie) {
+        const double bE = b * (4.0 * (geo.e0 + ie) - 2.0 * geo.N);
+        const double* __restrict__ row = lg + static_cast<int64_t>(ie) * nM;
+        double M = 2.0 * geo.m0 - 1.0 * geo.N;
+        int im = 0;
+        for (; im + 8 <= nM; im += 8) {
+            double l[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) l[k] = row[im + k];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                lse_step(l[k] - bE + bh * M, mx, sum);
+                M += 2.0;
             }
+        }
+        for (; im < nM; ++im) {
+            lse_step(row[im] - bE + bh * M, mx, sum);
+            M += 2.0;
         }
     }
     if (on) lnz[gp] = mx + log(sum);

@@ -137,6 +137,27 @@ def merge(pieces, N, norm="ground", errs=None):
     return joint, marginal(joint), e_mats, jerr
 
 
+def merge_m(pieces, N, norm="ground", errs=None):
+    """Join magnetization-window pieces (the alternative split of Sec. 2).
+
+    pieces: list (ordered by m) of (lo, hi, lng) with lng float64 of shape
+    (N + 1, hi - lo + 1): every energy row, the window's magnetization
+    columns.  The same steps as `merge` with the roles of E and M swapped:
+    marginal over E, ln g(M) = log sum_E g(E, M); matching point M_mat where
+    d ln g(M)/dM of the two pieces agree best; one additive constant per
+    piece; the piece below M_mat from the lower window.  Returns (lng_joint
+    (N+1, N+1) indexed [e, m], lng_marginal over M (ln g(E)), m_mats[, joint
+    error table])."""
+    tp = [(lo, hi, np.ascontiguousarray(t.T)) for lo, hi, t in pieces]
+    te = None if errs is None else [np.ascontiguousarray(e.T) for e in errs]
+    out = merge(tp, N, "sum", te)
+    joint = normalise(np.ascontiguousarray(out[0].T), N, norm)
+    res = (joint, marginal(joint), out[2])
+    if errs is None:
+        return res
+    return res + (np.ascontiguousarray(out[3].T),)
+
+
 def normalise(joint, N, norm="ground"):
     if norm == "sum":
         return joint - _lse(joint[np.isfinite(joint)]) + N * math.log(2.0)
@@ -160,4 +181,5 @@ def merge_oracle_run(orc, norm="ground", with_err=False):
         avg, err = window_average(frags, orc.K, with_err=True)
         pieces.append((lo, hi, avg))
         errs.append(err)
-    return merge(pieces, orc.N, norm, errs if with_err else None)
+    join = merge_m if getattr(orc, "split", 0) else merge
+    return join(pieces, orc.N, norm, errs if with_err else None)

@@ -76,6 +76,8 @@ def lib():
         L.or_set_stage.restype = None
         L.or_set_sync.argtypes = [C.c_void_p, C.c_int]
         L.or_set_sync.restype = C.c_int
+        L.or_set_split.argtypes = [C.c_void_p, C.c_int]
+        L.or_set_split.restype = C.c_int
         L.or_window_state.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int),
                                       C.POINTER(C.c_int)]
         L.or_window_state.restype = None
@@ -119,10 +121,15 @@ def energy(spins, L):
 
 # ---------------------------------------------------------------- simulation
 class OracleREWL:
-    """One 2D-REWL simulation (all windows and walkers of one problem)."""
+    """One 2D-REWL simulation (all windows and walkers of one problem).
+
+    split = 0: the windows split the energy range, every window keeping the
+    full magnetization range (the paper's runs, Sec. 3); split = 1: they split
+    the magnetization range and keep every energy (the alternative named at
+    the end of Sec. 2)."""
 
     def __init__(self, L, n_windows=1, overlap=(3, 4), walkers_per_window=1,
-                 k_final=16, flat=(4, 5), interval=10_000, seed=0, init=0, sync=0):
+                 k_final=16, flat=(4, 5), interval=10_000, seed=0, init=0, sync=0, split=0):
         self.L, self.N = L, L * L
         self.n_windows, self.W = n_windows, walkers_per_window
         self.K, self.X, self.seed = k_final, interval, seed
@@ -136,6 +143,9 @@ class OracleREWL:
         self.sync = sync
         if lib().or_set_sync(h, sync) != 0:
             raise ValueError("sync must be 0 (all windows together) or 1 (per window)")
+        self.split = split
+        if lib().or_set_split(h, split) != 0:
+            raise ValueError("split must be 0 (energy windows) or 1 (magnetization windows)")
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -189,7 +199,8 @@ class OracleREWL:
         """State of walker g = w * W + a as a dict of numpy arrays / ints."""
         w = g // self.W
         lo, hi = self.window(w)
-        shape = (hi - lo + 1, self.N + 1)
+        # rows e - lo by all m (energy windows), or all e by columns m - lo
+        shape = (self.N + 1, hi - lo + 1) if self.split else (hi - lo + 1, self.N + 1)
         lng = np.zeros(shape, np.int64) if tables else None
         H = np.zeros(shape, np.uint64) if tables else None
         sp = np.zeros(self.N, np.int8)

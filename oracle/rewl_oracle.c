@@ -20,7 +20,9 @@
  *   - on accept update g, H at the trial state, else at the current one (Sec. 2);
  *   - iterate until H is flat, then reset H and refine f -> sqrt(f) (Sec. 2);
  *   - 80 % flatness: every entry >= 0.8 * mean (Sec. 3);
- *   - overlapping equal-size energy windows, unrestricted M (Sec. 2, Sec. 3);
+ *   - overlapping equal-size energy windows, unrestricted M (Sec. 2, Sec. 3),
+ *     or, as the alternative Sec. 2 names, magnetization windows with
+ *     unrestricted E (or_set_split);
  *   - several independent walkers per window with their own g, H (Sec. 2);
  *   - configuration exchange between random walker pairs of adjacent windows,
  *     attempted only when both lie in the overlap, accepted with Eq. 2;
@@ -161,12 +163,17 @@ typedef struct {
     int64_t X;
     uint64_t seed;
     int nwalk;
-    int *lo, *hi;      /* window bounds in energy bins e = (E + 2N)/4 */
+    int split;         /* 0: windows split the energy bins e = (E + 2N)/4 (the
+                          paper's runs); 1: they split the magnetization bins
+                          m = (M + N)/2, every window keeping all energies */
+    int *lo, *hi;      /* window bounds in the split coordinate */
     int8_t *spin;      /* [nwalk][N] */
     int *e, *m;        /* current bins; m = (M + N)/2 */
     int64_t *t;        /* WL attempts made */
     int64_t *te;       /* entry attempts made */
-    int64_t **lng;     /* [nwalk][(hi-lo+1)(N+1)]  ln g in units 2^-K */
+    int64_t **lng;     /* [nwalk][(hi-lo+1)(N+1)]  ln g in units 2^-K: rows
+                          e - lo, columns m (split 0), or rows e, columns
+                          m - lo (split 1) */
     uint64_t **H;      /* same shape */
     uint8_t *flag;     /* flat in the current stage (latched) */
     int s;             /* stage: ln f = 2^-s (the lowest window stage) */
@@ -182,8 +189,11 @@ static int64_t bins_of(const or_rewl *P, int w) {
     return (int64_t)(P->hi[w] - P->lo[w] + 1) * (P->N + 1);
 }
 static int64_t bin_index(const or_rewl *P, int w, int e, int m) {
+    if (P->split) return (int64_t)e * (P->hi[w] - P->lo[w] + 1) + (m - P->lo[w]);
     return (int64_t)(e - P->lo[w]) * (P->N + 1) + m;
 }
+/* The coordinate the windows split: e, or m when split = 1. */
+static int coord(const or_rewl *P, int e, int m) { return P->split ? m : e; }
 
 OR_EXPORT void or_destroy(or_rewl *P) {
     if (!P) return;
@@ -266,13 +276,13 @@ static int site_of(uint32_t word, int N) {
 /* D-10  Initial configuration and entry into the walker's window.           */
 /* Spins: site 128q + 32j + k takes bit k of word j of INIT block q          */
 /* (1 -> +1), or all +1 when init = 1.  Entry: Metropolis at unit            */
-/* temperature on the distance d (in bins) from the energy window: a flip    */
-/* that does not increase d is accepted, one that increases it by k bins is  */
-/* accepted with exp(-4k); the walk stops once d = 0.                        */
+/* temperature on the distance d (in bins of the split coordinate) from the */
+/* window: a flip that does not increase d is accepted, one that increases   */
+/* it by k bins is accepted with exp(-4k); the walk stops once d = 0.        */
 /* ------------------------------------------------------------------------ */
-static int dist_to(const or_rewl *P, int w, int e) {
-    if (e < P->lo[w]) return P->lo[w] - e;
-    if (e > P->hi[w]) return e - P->hi[w];
+static int dist_to(const or_rewl *P, int w, int x) {
+    if (x < P->lo[w]) return P->lo[w] - x;
+    if (x > P->hi[w]) return x - P->hi[w];
     return 0;
 }
 
@@ -305,7 +315,7 @@ OR_EXPORT int or_init(or_rewl *P, int64_t entry_cap) {
         P->t[g] = 0;
         P->te[g] = 0;
         int w = win_of(P, g);
-        int d = dist_to(P, w, P->e[g]);
+        int d = dist_to(P, w, coord(P, P->e[g], P->m[g]));
         while (d > 0) {
             if (P->te[g] >= entry_cap) { bad |= 1; break; }
             uint32_t sw, uw;
@@ -313,7 +323,7 @@ OR_EXPORT int or_init(or_rewl *P, int64_t entry_cap) {
             int site = site_of(sw, N);
             int e2, m2;
             flip_target(P, s, site, P->e[g], P->m[g], &e2, &m2);
-            int d2 = dist_to(P, w, e2);
+            int d2 = dist_to(P, w, coord(P, e2, m2));
             int acc = d2 <= d ||
                       or_accept(-((int64_t)4 * (d2 - d)) * ((int64_t)1 << P->K),
                                 uw, P->K);
@@ -331,10 +341,10 @@ OR_EXPORT int or_init(or_rewl *P, int64_t entry_cap) {
 
 /* ------------------------------------------------------------------------ */
 /* D-8  One Wang-Landau trial (Sec. 2, Eq. 1): propose flipping a uniformly   */
-/* chosen site, reject a proposal that leaves the walker's energy window,    */
-/* otherwise accept with min[1, g(current)/g(trial)]; then multiply g by f   */
-/* (add ln f = 2^(K-s) units) and add one to H at the state the walker is in */
-/* after the decision.                                                        */
+/* chosen site, reject a proposal that leaves the walker's window (in e, or  */
+/* in m for split = 1), otherwise accept with min[1, g(current)/g(trial)];   */
+/* then multiply g by f (add ln f = 2^(K-s) units) and add one to H at the  */
+/* state the walker is in after the decision.                                */
 /* ------------------------------------------------------------------------ */
 static void wl_attempt(or_rewl *P, int g) {
     int N = P->N;
@@ -347,7 +357,8 @@ static void wl_attempt(or_rewl *P, int g) {
     int e2, m2;
     flip_target(P, s, site, e, m, &e2, &m2);
     int acc = 0;
-    if (e2 >= P->lo[w] && e2 <= P->hi[w]) {
+    int x2 = coord(P, e2, m2);
+    if (x2 >= P->lo[w] && x2 <= P->hi[w]) {
         int64_t delta = P->lng[g][bin_index(P, w, e, m)] -
                         P->lng[g][bin_index(P, w, e2, m2)];
         acc = or_accept(delta, uw, P->K);
@@ -400,7 +411,7 @@ OR_EXPORT int or_is_flat(const or_rewl *P, int g) {
 /* Round r pairs windows (w, w+1) with w = r (mod 2).  The walkers of w+1    */
 /* are matched to those of w by a Fisher-Yates permutation drawn from the    */
 /* XPERM stream; pair (A = (w,a), B = (w+1,pi[a])) is attempted only if A's  */
-/* energy lies in window w+1 and B's in window w, and is accepted with       */
+/* split coordinate lies in window w+1 and B's in window w, accepted with   */
 /* min[1, g_A(X) g_B(Y) / (g_A(Y) g_B(X))], X and Y being the configurations */
 /* A and B hold.  On accept the two configurations are swapped; neither      */
 /* ln g nor H changes.                                                        */
@@ -433,8 +444,9 @@ OR_EXPORT int64_t or_exchange(or_rewl *P, int64_t r) {
             int A = w * W + a, B = (w + 1) * W + pi[a];
             int eA = P->e[A], mA = P->m[A], eB = P->e[B], mB = P->m[B];
             if (P->wdone[w] || P->wdone[w + 1]) continue;
-            if (eA < P->lo[w + 1] || eA > P->hi[w + 1]) continue;
-            if (eB < P->lo[w] || eB > P->hi[w]) continue;
+            int xA = coord(P, eA, mA), xB = coord(P, eB, mB);
+            if (xA < P->lo[w + 1] || xA > P->hi[w + 1]) continue;
+            if (xB < P->lo[w] || xB > P->hi[w]) continue;
             int64_t delta = P->lng[A][bin_index(P, w, eA, mA)] -
                             P->lng[A][bin_index(P, w, eB, mB)] +
                             P->lng[B][bin_index(P, w + 1, eB, mB)] -
@@ -615,6 +627,16 @@ OR_EXPORT void or_set_stage(or_rewl *P, int s) {
 
 /* Choose how stages advance (before or_init): 0 = all windows together (the
  * paper, Sec. 2), 1 = each window alone, averaging its walkers' ln g. */
+/* Choose which coordinate the windows split (before or_init): 0 = energy,
+ * 1 = magnetization (the alternative split the paper names in Sec. 2).  The
+ * window bounds are the same D-6 formula over [0, N] either way, so the
+ * table sizes do not change. */
+OR_EXPORT int or_set_split(or_rewl *P, int split) {
+    if (split != 0 && split != 1) return -1;
+    P->split = split;
+    return 0;
+}
+
 OR_EXPORT int or_set_sync(or_rewl *P, int sync) {
     if (sync != 0 && sync != 1) return -1;
     P->sync = sync;

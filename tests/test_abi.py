@@ -97,3 +97,50 @@ def test_grid_reweighting_validation_on_host():
     assert L.rewl_lnz_grid_backward(fake, 16, 0, 17, 0, 17, fake, 4, fake, 4, fake, None, fake, 1 << 20,
                                     fake, None, None, None, None) == R.REWL_EINVAL
     assert L.rewl_last_error()
+
+
+def test_plan_create_fuzz_against_the_window_formula():
+    # random problems, valid and not: the host never crashes, rejects exactly the
+    # invalid ones, and its windows and table sizes follow the window formula
+    hyp = pytest.importorskip("hypothesis")
+    st = hyp.strategies
+    R, L = _lib()
+    from oracle.rewl import window
+    seen = {"ok": 0, "bad": 0}
+
+    @hyp.settings(max_examples=300, deadline=None, derandomize=True)
+    @hyp.given(Ls=st.integers(0, 70), nw=st.integers(-1, 80), on=st.integers(-1, 5), od=st.integers(0, 5),
+               W=st.integers(0, 260), K=st.integers(-1, 42))
+    def check(Ls, nw, on, od, W, K):
+        p = R.Problem(L=Ls, n_windows=nw, overlap=(on, od), walkers_per_window=W, k_final=K)
+        h = C.c_void_p()
+        arr = (R._Problem * 1)(p._c())
+        status = L.rewl_plan_create(arr, 1, None, C.byref(h))
+        valid = (4 <= Ls <= 64 and Ls % 2 == 0 and nw >= 1 and 1 <= od and 0 <= on < od and 1 <= W <= 256
+                 and 0 <= K <= 40)
+        N = Ls * Ls
+        if valid:
+            wins = [window(N, nw, on, od, w) for w in range(nw)]
+            valid = all(lo <= hi for lo, hi in wins)
+        if not valid:
+            assert status == R.REWL_EINVAL and L.rewl_last_error()
+            seen["bad"] += 1
+            return
+        assert status == R.REWL_OK
+        seen["ok"] += 1
+        try:
+            total = 0
+            for w, (lo, hi) in enumerate(wins):
+                a, b = C.c_int32(), C.c_int32()
+                assert L.rewl_window_bounds(h, 0, w, C.byref(a), C.byref(b)) == 0
+                assert (a.value, b.value) == (lo, hi)
+                total += -(-(hi - lo + 1) // 4) * -(-(N + 1) // 4) * 16 * W
+            sizes = (C.c_size_t * 3)()
+            assert L.rewl_plan_buffer_sizes(h, sizes) == 0
+            assert total * 16 <= sizes[0] < total * 16 + 256
+            assert sizes[1] >= nw * W * Ls * ((Ls + 31) // 32) * 4
+        finally:
+            L.rewl_plan_destroy(h)
+
+    check()
+    assert seen["ok"] >= 20 and seen["bad"] >= 20, seen

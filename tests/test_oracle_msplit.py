@@ -133,3 +133,19 @@ def test_msplit_full_4x4_run_against_enumeration():
         # statistical error of one run at ln f = 2^-16 (max 0.03-0.10, mean 0.009-0.02 over seeds 0-5)
         assert d.max() < 0.15 and d.mean() < 0.03, (seed, d.max(), d.mean())
         assert np.isneginf(joint[~ok]).all()
+
+
+def test_msplit_8x8_marginal_against_exact():
+    # 3 magnetization windows (overlap 3/4) x 2 walkers to ln f = 2^-10: the marginal
+    # g(E) = sum_M g(E, M) of the M-joined table against the exact finite-lattice g(E).
+    # Seeds 0-2 reach max |d ln g| 0.12-0.22 (the energy split: 0.15-0.35).
+    ex = exact.exact_lngE(8)
+    ok = np.isfinite(ex)
+    o = OracleREWL(8, 3, (3, 4), 2, 10, (4, 5), 1000, seed=0, split=1)
+    o.init()
+    o.run_to_end()
+    assert o.info()["done"]
+    joint, marg, m_mats = MG.merge_oracle_run(o, "sum")
+    assert (np.isfinite(marg) == ok).all()
+    d = np.abs(marg[ok] - ex[ok])
+    assert d.max() < 0.6 and d.mean() < 0.1, (d.max(), d.mean())

@@ -60,7 +60,8 @@ typedef enum {
 /* One REWL simulation -- the paper's problem statement (Sec. 2, Sec. 3). */
 typedef struct {
     int32_t L;                   /* even, 4..64: periodic L x L, J = 1, h = 0 while sampling */
-    int32_t n_windows;           /* >= 1 energy windows, full M range each (Sec. 3) */
+    int32_t n_windows;           /* >= 1 windows in the split coordinate (energy: full M
+                                    range each, Sec. 3) */
     int32_t overlap_num;         /* overlap of neighbouring windows = num/den, */
     int32_t overlap_den;         /*   e.g. 3/4, or 1/2 as in the paper's runs */
     int32_t walkers_per_window;  /* >= 1, independent g and H each (Sec. 2); <= 256 */
@@ -72,6 +73,9 @@ typedef struct {
     uint64_t seed;               /* Philox key */
     int32_t init;                /* 0: spins Bernoulli(1/2) from Philox; 1: all +1 */
     int32_t stage_sync;          /* REWL_SYNC_PROBLEM (the paper) or REWL_SYNC_WINDOW */
+    int32_t split;               /* REWL_SPLIT_ENERGY (the paper's runs) or
+                                    REWL_SPLIT_MAGNETIZATION; one value per plan */
+    int32_t reserved;            /* must be 0 */
 } rewl_problem;
 
 /* How ln f is refined (rewl_problem.stage_sync).
@@ -86,6 +90,19 @@ typedef struct {
  *     problem ends with its last window.  (The common REWL form the paper
  *     cites, Sec. 1; not the paper's own runs.) */
 enum { REWL_SYNC_PROBLEM = 0, REWL_SYNC_WINDOW = 1 };
+
+/* Which coordinate the windows split (rewl_problem.split).
+ *   REWL_SPLIT_ENERGY: windows over the energy bins e, each with the full
+ *     magnetization range (Sec. 2, Sec. 3; the paper's runs).  A walker's
+ *     tables are indexed [e - lo][m].
+ *   REWL_SPLIT_MAGNETIZATION: windows over the magnetization bins m with the
+ *     same overlapping-window formula, each keeping every energy (the
+ *     alternative split named at the end of Sec. 2).  A proposal leaving the
+ *     window in m is rejected; the entry walk and the exchange overlap test
+ *     use m.  Tables are indexed [e][m - lo].  rewl_merge_lng joins energy
+ *     windows only.
+ * All problems of one plan use the same split. */
+enum { REWL_SPLIT_ENERGY = 0, REWL_SPLIT_MAGNETIZATION = 1 };
 
 /* Execution form and tuning.  None of these change results. */
 enum { REWL_FORM_BATCHED = 0, REWL_FORM_PLAIN = 1 };
@@ -129,7 +146,8 @@ rewl_status rewl_plan_buffer_sizes(const rewl_plan* plan, size_t* sizes_out);
  * sizes above) and the hipStream_t to enqueue on (NULL = default stream). */
 rewl_status rewl_plan_bind(rewl_plan* plan, void* const* dev_ptrs, void* hip_stream);
 
-/* Energy-bin bounds [E_lo, E_hi] of window w of problem prob. */
+/* Bounds [lo, hi] of window w of problem prob, in energy bins (energy split)
+ * or magnetization bins (magnetization split). */
 rewl_status rewl_window_bounds(const rewl_plan* plan, int32_t prob, int32_t w,
                                int32_t* e_lo, int32_t* e_hi);
 
@@ -167,8 +185,9 @@ rewl_status rewl_query_windows(rewl_plan* plan, int32_t prob, int32_t* stage_out
                                int64_t* trials_out);
 
 /* State of walker a of window w of problem prob.  lng and H (nullable) get the
- * window table, (E_hi - E_lo + 1) x (N + 1) row-major by (e - E_lo, m), with
- * cap_bins entries of room; spins (nullable) gets N bytes +1/-1 in row-major
+ * window table with cap_bins entries of room: (hi - lo + 1) x (N + 1)
+ * row-major by (e - lo, m) for the energy split, (N + 1) x (hi - lo + 1) by
+ * (e, m - lo) for the magnetization split; spins (nullable) gets N bytes +1/-1 in row-major
  * site order; e, m, t (nullable) the current bins and trial count.
  * Synchronises. */
 rewl_status rewl_read_walker(rewl_plan* plan, int32_t prob, int32_t w, int32_t a,

@@ -24,6 +24,7 @@ REWL_OK, REWL_EINVAL, REWL_ENOMEM, REWL_EDEVICE, REWL_ESTATE, REWL_EOVERFLOW, RE
     0, -1, -2, -3, -4, -5, -6
 FORM_BATCHED, FORM_PLAIN = 0, 1
 SYNC_PROBLEM, SYNC_WINDOW = 0, 1
+SPLIT_ENERGY, SPLIT_MAGNETIZATION = 0, 1
 NBUF = 3
 
 
@@ -37,7 +38,8 @@ class _Problem(C.Structure):
     _fields_ = [("L", C.c_int32), ("n_windows", C.c_int32), ("overlap_num", C.c_int32),
                 ("overlap_den", C.c_int32), ("walkers_per_window", C.c_int32), ("k_final", C.c_int32),
                 ("flat_num", C.c_int32), ("flat_den", C.c_int32), ("interval", C.c_int64),
-                ("seed", C.c_uint64), ("init", C.c_int32), ("stage_sync", C.c_int32)]
+                ("seed", C.c_uint64), ("init", C.c_int32), ("stage_sync", C.c_int32),
+                ("split", C.c_int32), ("reserved", C.c_int32)]
 
 
 class _Tuning(C.Structure):
@@ -111,7 +113,9 @@ class Problem:
     """One REWL simulation (Sec. 2 of the paper; defaults: 80 % flatness).
 
     stage_sync: SYNC_PROBLEM (all windows refine ln f together, the paper) or
-    SYNC_WINDOW (each window averages its walkers' ln g and refines alone)."""
+    SYNC_WINDOW (each window averages its walkers' ln g and refines alone).
+    split: SPLIT_ENERGY (windows over E, the paper's runs) or SPLIT_MAGNETIZATION
+    (windows over M with every energy, the alternative of Sec. 2); one per plan."""
     L: int
     n_windows: int = 1
     overlap: tuple = (3, 4)
@@ -122,11 +126,12 @@ class Problem:
     seed: int = 0
     init: int = 0
     stage_sync: int = SYNC_PROBLEM
+    split: int = SPLIT_ENERGY
 
     def _c(self):
         return _Problem(self.L, self.n_windows, self.overlap[0], self.overlap[1], self.walkers_per_window,
                         self.k_final, self.flat[0], self.flat[1], self.interval,
-                        self.seed & 0xFFFFFFFFFFFFFFFF, self.init, self.stage_sync)
+                        self.seed & 0xFFFFFFFFFFFFFFFF, self.init, self.stage_sync, self.split, 0)
 
     @property
     def N(self):
@@ -269,7 +274,8 @@ class Plan:
         return lo.value, hi.value
 
     def walker(self, prob, w, a, tables=True):
-        """Walker a of window w of problem prob: lng / H tables (rows e-lo, cols m), spins, e, m, t."""
+        """Walker a of window w of problem prob: lng / H tables (rows e - lo, cols m; for the
+        magnetization split rows e, cols m - lo), spins, e, m, t."""
         p = self.problems[prob]
         lo, hi = self.window(prob, w)
         nb = (hi - lo + 1) * (p.N + 1)
@@ -281,7 +287,7 @@ class Plan:
                                       lng.ctypes.data if tables else None,
                                       H.ctypes.data if tables else None, nb if tables else 0,
                                       sp.ctypes.data, C.byref(e), C.byref(m), C.byref(t)))
-        shape = (hi - lo + 1, p.N + 1)
+        shape = (p.N + 1, hi - lo + 1) if p.split else (hi - lo + 1, p.N + 1)
         return {"lng": None if lng is None else lng.reshape(shape),
                 "H": None if H is None else H.reshape(shape),
                 "spins": sp.reshape(p.L, p.L), "e": e.value, "m": m.value, "t": t.value,

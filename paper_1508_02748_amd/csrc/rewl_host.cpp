@@ -57,6 +57,7 @@ struct rewl_plan {
            off_nseen = 0, off_flag = 0, off_scan = 0, off_stage = 0, off_wdone = 0, off_tstage = 0, off_adv = 0,
            off_lngb = 0, off_tseen = 0, off_done = 0, off_rnd = 0, off_xr = 0, off_xon = 0, off_cnt = 0;
     int32_t n_win = 0;  // windows over all problems
+    int split = 0;      // the split of every problem of the plan (energy 0, magnetization 1)
     // binding
     bool bound = false;
     bool broken = false;
@@ -107,6 +108,9 @@ rewl_status validate(const rewl_problem& q, int idx) {
     if (q.init != 0 && q.init != 1) return bad("init must be 0 or 1");
     if (q.stage_sync != REWL_SYNC_PROBLEM && q.stage_sync != REWL_SYNC_WINDOW)
         return bad("stage_sync must be REWL_SYNC_PROBLEM or REWL_SYNC_WINDOW");
+    if (q.split != REWL_SPLIT_ENERGY && q.split != REWL_SPLIT_MAGNETIZATION)
+        return bad("split must be REWL_SPLIT_ENERGY or REWL_SPLIT_MAGNETIZATION");
+    if (q.reserved != 0) return bad("reserved must be 0");
     const int N = q.L * q.L;
     for (int i = 0; i < q.n_windows; ++i) {
         int lo, hi;
@@ -191,7 +195,7 @@ int max_grid_of(const rewl_plan* P) {
 rewl_status enqueue_sweep(rewl_plan* P, int64_t n, int ev_slot = -1) {
     if (ev_slot >= 0) HIPCHK(P, hipEventRecord(P->ev[2 * ev_slot], P->stream), "event record");
     HIPCHK(P, launch_sweep(P->S, 0, P->n_walk, n, P->l_max, wg_of(P), max_grid_of(P), P->tune.walkers_per_wave,
-                           P->stream), "sweep launch");
+                           P->split, P->stream), "sweep launch");
     if (ev_slot >= 0) HIPCHK(P, hipEventRecord(P->ev[2 * ev_slot + 1], P->stream), "event record");
     return REWL_OK;
 }
@@ -243,7 +247,7 @@ rewl_status run_interval_plain(rewl_plan* P) {
         const PDesc& q = P->pd[p];
         for (int w = 0; w < q.nwin; ++w) {
             HIPCHK(P, launch_sweep(P->S, q.walker_off + static_cast<int64_t>(w) * q.W, q.W, P->interval,
-                                   q.L, wg, 0, P->tune.walkers_per_wave, P->stream), "plain sweep launch");
+                                   q.L, wg, 0, P->tune.walkers_per_wave, P->split, P->stream), "plain sweep launch");
         }
     }
     HIPCHK(P, launch_flat(P->S, P->stream), "flatness launch");
@@ -399,6 +403,9 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
     const int64_t X = problems[0].interval;
     for (int i = 1; i < n_problems; ++i)
         if (problems[i].interval != X) return fail(REWL_EINVAL, "all problems of a plan must share the interval");
+    for (int i = 1; i < n_problems; ++i)
+        if (problems[i].split != problems[0].split)
+            return fail(REWL_EINVAL, "all problems of a plan must share the split");
 
     rewl_plan* P = new (std::nothrow) rewl_plan();
     if (!P) return fail(REWL_ENOMEM, "plan allocation");
@@ -406,6 +413,7 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
     P->tune = tn;
     P->profile = tn.profile != 0;
     P->interval = X;
+    P->split = problems[0].split;
     int64_t walker = 0;
     uint64_t bins = 0, words = 0;
     for (int p = 0; p < n_problems; ++p) {
@@ -424,7 +432,8 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
         d.walker_off = static_cast<int32_t>(walker);
         d.init = q.init;
         d.win_off = P->n_win;
-        d.sync = q.stage_sync;
+        d.sync = static_cast<int16_t>(q.stage_sync);
+        d.split = static_cast<int16_t>(q.split);
         P->pd.push_back(d);
         P->l_max = std::max(P->l_max, q.L);
         std::vector<int> los, his;
@@ -442,8 +451,11 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
                 wd.hi = hi;
                 wd.win = w;
                 wd.gid = w * q.walkers_per_window + a;
-                wd.ntm = static_cast<uint32_t>((d.N + 1 + TILE_M - 1) / TILE_M);
-                wd.nbins = static_cast<uint32_t>((hi - lo + 1 + TILE_E - 1) / TILE_E) * wd.ntm * TILE_BINS;
+                // rows e - lo, all m (energy windows) or all e, columns m - lo (magnetization)
+                const int rows = q.split ? d.N + 1 : hi - lo + 1;
+                const int cols = q.split ? hi - lo + 1 : d.N + 1;
+                wd.ntm = static_cast<uint32_t>((cols + TILE_M - 1) / TILE_M);
+                wd.nbins = static_cast<uint32_t>((rows + TILE_E - 1) / TILE_E) * wd.ntm * TILE_BINS;
                 wd.gwin = P->n_win + w;
                 P->wd.push_back(wd);
                 bins += wd.nbins;
@@ -603,7 +615,7 @@ rewl_status rewl_sweep(rewl_plan* P, int64_t n) {
         for (const PDesc& q : P->pd)
             for (int w = 0; w < q.nwin; ++w)
                 HIPCHK(P, launch_sweep(P->S, q.walker_off + static_cast<int64_t>(w) * q.W, q.W, n, q.L, wg, 0,
-                                       P->tune.walkers_per_wave, P->stream), "plain sweep launch");
+                                       P->tune.walkers_per_wave, P->split, P->stream), "plain sweep launch");
         return REWL_OK;
     }
     return enqueue_sweep(P, n);
@@ -710,7 +722,8 @@ rewl_status rewl_read_walker(rewl_plan* P, int32_t prob, int32_t w, int32_t a, i
     if (w < 0 || w >= q.nwin || a < 0 || a >= q.W) return fail(REWL_EINVAL, "walker out of range");
     const int64_t g = q.walker_off + static_cast<int64_t>(w) * q.W + a;
     const WDesc& d = P->wd[g];
-    const int nE = d.hi - d.lo + 1, nM = q.N + 1;
+    const int nE = q.split ? q.N + 1 : d.hi - d.lo + 1;  // rows of the dense output
+    const int nM = q.split ? d.hi - d.lo + 1 : q.N + 1;  // columns
     const size_t nb = static_cast<size_t>(nE) * nM;
     if ((lng || H) && cap_bins < nb) return fail(REWL_EINVAL, "cap_bins too small");
     std::vector<int64_t> tl, ts;
@@ -930,6 +943,7 @@ extern "C" rewl_status rewl_merge_lng(rewl_plan* P, int32_t prob, int32_t norm, 
     if (!P->initialised) return fail(REWL_ESTATE, "rewl_init has not run");
     if (norm != 0 && norm != 1) return fail(REWL_EINVAL, "norm must be 0 (ground state) or 1 (sum)");
     if (!workspace || !lng_out || !lnge_out) return fail(REWL_EINVAL, "null device pointer");
+    if (P->split) return fail(REWL_EINVAL, "the device merge joins energy windows only");
     MergeLayout ml;
     if ((s = merge_layout(P, prob, static_cast<char*>(workspace), ml)) != REWL_OK) return s;
     if (ws_bytes < ml.bytes) return fail(REWL_EINVAL, "workspace too small");
@@ -963,7 +977,7 @@ extern "C" rewl_status rewl_set_tuning(rewl_plan* P, const rewl_tuning* tuning) 
 }
 
 namespace {
-constexpr uint64_t SAVE_MAGIC = 0x3230574C57455232ull;  // "2REWLW02": per-window stage state
+constexpr uint64_t SAVE_MAGIC = 0x3330574C57455232ull;  // "2REWLW03": problems carry the split
 struct SaveHeader {
     uint64_t magic;
     uint64_t n_problems;

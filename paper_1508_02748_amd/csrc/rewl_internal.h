@@ -6,8 +6,10 @@
 
 namespace rewl {
 
-// Window tables.  Each walker owns two int64 tables over its window rows
-// e in [lo, hi] and all m in [0, N]: ln g in units of 2^-K (> 0 marks a bin
+// Window tables.  Each walker owns two int64 tables over its window: rows
+// e in [lo, hi] and all m in [0, N] when the windows split the energy, or all
+// rows e in [0, N] and columns m in [lo, hi] when they split the
+// magnetization: ln g in units of 2^-K (> 0 marks a bin
 // the walker has visited; ln g only grows), and a snapshot of ln g taken when
 // the current stage began.  Every visit in stage s adds 2^(K-s), so the visit
 // count of the stage is H = (ln g - snapshot) >> (K - s): a trial touches only
@@ -29,11 +31,13 @@ struct WDesc {
                          // offset of the snapshot table)
     uint32_t spin_off;   // first word of its L x row_words packed spins
     int32_t prob;        // problem index
-    int32_t lo, hi;      // energy-bin window
+    int32_t lo, hi;      // window in the split coordinate (e, or m for the magnetization split);
+                         // the table's row is e - lo, column m (energy split), or row e,
+                         // column m - lo (magnetization split)
     int32_t win;         // window index within the problem
     int32_t gid;         // walker id within the problem: win * W + a
-    uint32_t ntm;        // tiles per energy row = ceil((N + 1) / 4)
-    uint32_t nbins;      // bins of its tiled table = ceil((hi - lo + 1) / 4) * ntm * 16
+    uint32_t ntm;        // tiles per table row = ceil(columns / 4)
+    uint32_t nbins;      // bins of its tiled table = ceil(rows / 4) * ntm * 16
     int32_t gwin;        // window index over all problems of the plan
 };
 
@@ -45,7 +49,8 @@ struct PDesc {
     int32_t walker_off;  // first global walker index
     int32_t init;
     int32_t win_off;     // first global window index
-    int32_t sync;        // 0: all windows change stage together; 1: each window alone
+    int16_t sync;        // 0: all windows change stage together; 1: each window alone
+    int16_t split;       // 0: energy windows; 1: magnetization windows
 };
 
 // A window pair (w, w+1) of one problem that may exchange configurations.
@@ -112,7 +117,7 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_init(const DevState& S, hipStream_t st);
 hipError_t launch_entry(const DevState& S, int64_t cap, hipStream_t st);
 hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int64_t n_trials,
-                        int l_max, int wg, int max_grid, int wpw, hipStream_t st);
+                        int l_max, int wg, int max_grid, int wpw, int split, hipStream_t st);
 hipError_t sweep_setup();
 hipError_t launch_flat(const DevState& S, hipStream_t st);
 hipError_t launch_stage(const DevState& S, hipStream_t st);

@@ -198,7 +198,7 @@ __global__ void k_entry(DevState S, int64_t cap) {
     const WDesc d = S.wd[g];
     const PDesc P = S.pd[d.prob];
     int e = S.e[g], m = S.m[g];
-    int dist = win_dist(e, d.lo, d.hi);
+    int dist = win_dist(P.split ? m : e, d.lo, d.hi);  // distance in the split coordinate
     if (dist == 0) return;
     const int L = P.L, rw = P.row_words, K = P.K;
     uint32_t* sp = S.spins + d.spin_off;
@@ -218,7 +218,7 @@ __global__ void k_entry(DevState S, int64_t cap) {
                            (gbit(sp, rw, r == L - 1 ? 0 : r + 1, c) ^ bc);
         const int e2 = e + 2 - static_cast<int>(k);
         const int m2 = m + 1 - 2 * static_cast<int>(bc);
-        const int dist2 = win_dist(e2, d.lo, d.hi);
+        const int dist2 = win_dist(P.split ? m2 : e2, d.lo, d.hi);
         const bool acc = dist2 <= dist ||
                          accept_move(-static_cast<int64_t>(4 * (dist2 - dist)) * (static_cast<int64_t>(1) << K),
                                      uw, K);
@@ -300,7 +300,7 @@ __device__ __forceinline__ void pin(NoRounds&, int64_t& v, float& f) {
 // workgroup of WG lanes).  Its spins sit in LDS column `lane`; no lane touches
 // another's data, so there are no barriers.  The bin the walker occupies is
 // held in registers and written back when the walker leaves it.
-template <typename RowT>
+template <typename RowT, int SPLIT>
 __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int lane, int WG, int64_t g,
                                              int64_t n_trials) {
     const WDesc d = S.wd[g];
@@ -329,7 +329,8 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
     int e = S.e[g], m = S.m[g];
     int64_t t = S.t[g];
     uint32_t nseen = S.nseen[g];
-    uint32_t cur = tile_index(e - lo, m, ntm);
+    // table origin: rows e - lo by all m (energy windows), or all e by m - lo
+    uint32_t cur = SPLIT ? tile_index(e, m - lo, ntm) : tile_index(e - lo, m, ntm);
     int64_t lng_cur = tab[cur];
 
     // One trial with the words (sw, uw) of its Philox block; `q` (a PhiloxRun)
@@ -352,9 +353,11 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
                            ((static_cast<uint32_t>(rowd >> c) & 1u) ^ bc);
         const int e2 = e + 2 - static_cast<int>(k);       // dE = 8 - 4k
         const int m2 = m + 1 - 2 * static_cast<int>(bc);  // dM = -2 s
-        const bool in = e2 >= lo && e2 <= hi;
-        // gather unconditionally (a bin of the current row when out of the window)
-        const uint32_t idx2 = tile_index((in ? e2 : e) - lo, m2, ntm);
+        const int x2 = SPLIT ? m2 : e2;  // the coordinate the windows split
+        const bool in = x2 >= lo && x2 <= hi;
+        // gather unconditionally (a bin of the current row, or column, when out of the window)
+        const uint32_t idx2 = SPLIT ? tile_index(e2, (in ? m2 : m) - lo, ntm)
+                                    : tile_index((in ? e2 : e) - lo, m2, ntm);
         int64_t lng2 = tab[idx2];
         const double u = __dmul_rn(__dadd_rn(static_cast<double>(uw), 0.5), 1.0 / 4294967296.0);
         float uf = static_cast<float>(u);
@@ -420,7 +423,7 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
 // walkers in flight and so the set of table lines competing for the L2; the
 // tile-to-workgroup map is the same at every launch, so a walker stays on the
 // same XCD.
-template <typename RowT>
+template <typename RowT, int SPLIT>
 __global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int64_t g_count,
                                                int64_t n_trials, int wpw) {
     extern __shared__ unsigned char lds_raw[];
@@ -434,7 +437,7 @@ __global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int6
     const int64_t n_tiles = (g_count + per - 1) / per;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t gi = tile * per + wave * wpw + wl;
-        if (wl < wpw && gi < g_count) sweep_walker<RowT>(S, lds, lane, WG, g_begin + gi, n_trials);
+        if (wl < wpw && gi < g_count) sweep_walker<RowT, SPLIT>(S, lds, lane, WG, g_begin + gi, n_trials);
     }
 }
 
@@ -681,11 +684,16 @@ __global__ void __launch_bounds__(64) k_exchange(DevState S) {
             const int B = P.walker_off + (w + 1) * W + perm[a];
             const WDesc dA = S.wd[A], dB = S.wd[B];
             const int eA = S.e[A], mA = S.m[A], eB = S.e[B], mB = S.m[B];
-            if (eA < dB.lo || eA > dB.hi || eB < dA.lo || eB > dA.hi) continue;
+            const int xA = P.split ? mA : eA, xB = P.split ? mB : eB;  // split coordinate
+            if (xA < dB.lo || xA > dB.hi || xB < dA.lo || xB > dA.hi) continue;
             const int64_t* tA = S.lng + dA.table_off;
             const int64_t* tB = S.lng + dB.table_off;
-            const int64_t delta = tA[tile_index(eA - dA.lo, mA, dA.ntm)] - tA[tile_index(eB - dA.lo, mB, dA.ntm)] +
-                                  tB[tile_index(eB - dB.lo, mB, dB.ntm)] - tB[tile_index(eA - dB.lo, mA, dB.ntm)];
+            // table origins: (lo, 0) for energy windows, (0, lo) for magnetization windows
+            const int eoA = P.split ? 0 : dA.lo, moA = P.split ? dA.lo : 0;
+            const int eoB = P.split ? 0 : dB.lo, moB = P.split ? dB.lo : 0;
+            const int64_t delta =
+                tA[tile_index(eA - eoA, mA - moA, dA.ntm)] - tA[tile_index(eB - eoA, mB - moA, dA.ntm)] +
+                tB[tile_index(eB - eoB, mB - moB, dB.ntm)] - tB[tile_index(eA - eoB, mA - moB, dB.ntm)];
             const Words4 b = philox4x32_10(P.seed, r_lo, r_hi, static_cast<uint32_t>(w),
                                            (TAG_XACC << 24) | static_cast<uint32_t>(a));
             if (accept_move(delta, b.x, P.K)) {
@@ -737,27 +745,33 @@ hipError_t launch_entry(const DevState& S, int64_t cap, hipStream_t st) {
 }
 
 hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int64_t n_trials,
-                        int l_max, int wg, int max_grid, int wpw, hipStream_t st) {
+                        int l_max, int wg, int max_grid, int wpw, int split, hipStream_t st) {
     if (g_count <= 0 || n_trials <= 0) return hipSuccess;
     if (wpw <= 0 || wpw > 64) wpw = 64;
     int grid = blocks_for(g_count, (wg / 64) * wpw);
     if (max_grid > 0 && grid > max_grid) grid = max_grid;
-    if (l_max <= 32) {
-        const size_t lds = static_cast<size_t>(l_max) * wg * sizeof(uint32_t);
-        hipLaunchKernelGGL(k_sweep<uint32_t>, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
-    } else {
-        const size_t lds = static_cast<size_t>(l_max) * wg * sizeof(uint64_t);
-        hipLaunchKernelGGL(k_sweep<uint64_t>, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
-    }
+    const size_t lds = static_cast<size_t>(l_max) * wg * (l_max <= 32 ? sizeof(uint32_t) : sizeof(uint64_t));
+    if (l_max <= 32 && !split)
+        hipLaunchKernelGGL((k_sweep<uint32_t, 0>), dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
+    else if (!split)
+        hipLaunchKernelGGL((k_sweep<uint64_t, 0>), dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
+    else if (l_max <= 32)
+        hipLaunchKernelGGL((k_sweep<uint32_t, 1>), dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
+    else
+        hipLaunchKernelGGL((k_sweep<uint64_t, 1>), dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
     return hipGetLastError();
 }
 
 hipError_t sweep_setup() {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep<uint32_t>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep<uint64_t>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    const void* fns[4] = {reinterpret_cast<const void*>(&k_sweep<uint32_t, 0>),
+                          reinterpret_cast<const void*>(&k_sweep<uint64_t, 0>),
+                          reinterpret_cast<const void*>(&k_sweep<uint32_t, 1>),
+                          reinterpret_cast<const void*>(&k_sweep<uint64_t, 1>)};
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_flat(const DevState& S, hipStream_t st) {

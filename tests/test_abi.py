@@ -144,3 +144,29 @@ def test_plan_create_fuzz_against_the_window_formula():
 
     check()
     assert seen["ok"] >= 20 and seen["bad"] >= 20, seen
+
+
+def test_split_validation_on_host():
+    R, L = _lib()
+    h = C.c_void_p()
+    for bad in (dict(L=8, split=2), dict(L=8, split=-1)):
+        arr = (R._Problem * 1)(R.Problem(**bad)._c())
+        assert L.rewl_plan_create(arr, 1, None, C.byref(h)) == R.REWL_EINVAL
+    arr = (R._Problem * 2)(R.Problem(L=8)._c(), R.Problem(L=8, split=R.SPLIT_MAGNETIZATION)._c())
+    assert L.rewl_plan_create(arr, 2, None, C.byref(h)) == R.REWL_EINVAL
+    c = R.Problem(L=8)._c()
+    c.reserved = 1
+    assert L.rewl_plan_create((R._Problem * 1)(c), 1, None, C.byref(h)) == R.REWL_EINVAL
+    # magnetization windows: all 65 energy rows by the window's m columns, in 4 x 4 tiles
+    arr = (R._Problem * 1)(R.Problem(L=8, n_windows=3, overlap=(1, 2), walkers_per_window=2,
+                                     split=R.SPLIT_MAGNETIZATION)._c())
+    assert L.rewl_plan_create(arr, 1, None, C.byref(h)) == R.REWL_OK
+    try:
+        from oracle.rewl import window
+        sizes = (C.c_size_t * 3)()
+        assert L.rewl_plan_buffer_sizes(h, sizes) == 0
+        bins = sum(-(-65 // 4) * -(-(window(64, 3, 1, 2, w)[1] - window(64, 3, 1, 2, w)[0] + 1) // 4) * 16 * 2
+                   for w in range(3))
+        assert bins * 16 <= sizes[0] < bins * 16 + 256
+    finally:
+        L.rewl_plan_destroy(h)

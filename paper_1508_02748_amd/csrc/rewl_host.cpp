@@ -917,9 +917,11 @@ rewl_status merge_layout(const rewl_plan* P, int32_t prob, char* base, MergeLayo
     // integer region (256-byte aligned): 4 flags (16 bytes, cleared with one
     // 16-byte store), then the matching points
     out.bytes = dbl_bytes + align_up(16 + static_cast<size_t>(q.nwin) * sizeof(int32_t), 256);
-    G.ws = reinterpret_cast<double*>(base);
-    G.flags = reinterpret_cast<int32_t*>(base + dbl_bytes);
-    G.emat = G.flags + 4;
+    if (base) {  // sizes only when no workspace is given
+        G.ws = reinterpret_cast<double*>(base);
+        G.flags = reinterpret_cast<int32_t*>(base + dbl_bytes);
+        G.emat = G.flags + 4;
+    }
     out.G = G;
     out.max_nE = max_nE;
     return REWL_OK;

@@ -33,7 +33,8 @@ def _key(plan):
     for p in plan.problems:
         sizes[p.L] = sizes.get(p.L, 0) + p.n_windows * p.walkers_per_window
     mix = ",".join(f"{L}:{n}" for L, n in sorted(sizes.items()))
-    return f"{name}|{mix}|{plan.n_walkers}|{plan.problems[0].interval}"
+    split = getattr(plan.problems[0], "split", 0)
+    return f"{name}|{mix}|{plan.n_walkers}|{plan.problems[0].interval}|split{split}"
 
 
 def _load_cache(path):

@@ -23,6 +23,16 @@ TEST INFRASTRUCTURE ONLY (pins for the oracle, see ``oracle/__init__.py``).
   complex plane with mpmath at N + 96 bits, and the coefficients are recovered
   by an inverse discrete Fourier transform and rounded to integers.
 
+* ``support_envelope(L)``: for every magnetization bin, the lowest and highest
+  realizable energy bin.  With k = min(m, N - m) minority spins, the fewest
+  unsatisfied bonds are those of the shortest closed domain wall around k
+  sites on the torus, P_min(k) = min(2 ceil(2 sqrt k), 2L + 2 [L does not
+  divide k]) (a compact cluster, or a band wrapping the torus once k >= L),
+  and the most are 4k (minority spins on one sublattice, none adjacent), so
+  e = P/2 runs from P_min/2 to 2k.  The realizable bins fill this range except
+  a few holes next to m = N/2.  The bounds say where windows in both E and M
+  hold states.
+
 Both are checked against each other at L = 4, against sum g = 2^N, the E -> -E
 symmetry and the counts of the lowest excitations (tests/test_exact.py).
 """
@@ -120,3 +130,22 @@ def binomial_lng(N):
     """ln C(N, m) for m = 0..N (the number of configurations with m up spins)."""
     return np.array([math.lgamma(N + 1) - math.lgamma(m + 1) - math.lgamma(N - m + 1)
                      for m in range(N + 1)])
+
+
+def support_envelope(L):
+    """(e_min, e_max): int arrays over m = 0..N of the lowest and highest
+    realizable energy bin at magnetization bin m (see the module notes)."""
+    N = L * L
+    e_min = np.zeros(N + 1, np.int64)
+    e_max = np.zeros(N + 1, np.int64)
+    for m in range(N + 1):
+        k = min(m, N - m)
+        if k == 0:
+            p_min = 0
+        else:
+            p_min = 2 * (math.isqrt(4 * k - 1) + 1)          # 2 ceil(2 sqrt k)
+            if k >= L:
+                p_min = min(p_min, 2 * L + (0 if k % L == 0 else 2))
+        e_min[m] = p_min // 2
+        e_max[m] = 2 * k
+    return e_min, e_max

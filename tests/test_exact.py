@@ -59,3 +59,19 @@ def test_golden_exact_lng_matches(golden_dir):
         fin = np.isfinite(ref)
         assert (np.isfinite(got) == fin).all()
         assert np.allclose(got[fin], ref[fin], rtol=0, atol=1e-12)
+
+
+def test_support_envelope_against_enumeration_4x4():
+    # lowest and highest realizable energy per magnetization, by brute force; the
+    # realizable energies fill the range except holes next to m = N/2 only
+    from oracle.exact import enumerate_joint, support_envelope
+    G = enumerate_joint(4)
+    e_min, e_max = support_envelope(4)
+    for m in range(17):
+        es = np.nonzero(G[:, m])[0]
+        assert (es.min(), es.max()) == (e_min[m], e_max[m]), m
+        holes = sorted(set(range(e_min[m], e_max[m] + 1)) - set(es.tolist()))
+        if abs(m - 8) > 1:
+            assert holes == [], (m, holes)
+    # the holes of this lattice: one below the top at m = 7, 9; three at m = 8
+    assert sorted(set(range(e_min[8], e_max[8] + 1)) - set(np.nonzero(G[:, 8])[0].tolist())) == [5, 14, 15]

@@ -158,6 +158,33 @@ def merge_m(pieces, N, norm="ground", errs=None):
     return res + (np.ascontiguousarray(out[3].T),)
 
 
+def merge_2d(pieces, N, norm="ground"):
+    """Join rectangular (E, M) pieces (windows in both coordinates, Sec. 2 end).
+
+    pieces: list of (e_lo, e_hi, m_lo, m_hi, lng) with lng float64 of shape
+    (e_hi - e_lo + 1, m_hi - m_lo + 1), -inf = unvisited.  The pieces of each
+    magnetization column (same m range) are first joined along E as energy
+    windows (E_mat from ln g(E) = log sum over the column's M), then the
+    columns are joined along M (M_mat from ln g(M) = log sum over E).
+    Returns (lng_joint (N+1, N+1), ln g(E), (E_mat lists per column, M_mat
+    list))."""
+    cols = {}
+    for elo, ehi, mlo, mhi, t in pieces:
+        cols.setdefault((mlo, mhi), []).append((elo, ehi, t))
+    col_pieces, e_mats = [], []
+    for (mlo, mhi) in sorted(cols):
+        rows = []
+        for elo, ehi, t in sorted(cols[(mlo, mhi)], key=lambda x: x[0]):
+            f = np.full((ehi - elo + 1, N + 1), -np.inf)
+            f[:, mlo:mhi + 1] = t
+            rows.append((elo, ehi, f))
+        joint_c, _, em = merge(rows, N, "sum")
+        col_pieces.append((mlo, mhi, joint_c[:, mlo:mhi + 1]))
+        e_mats.append(em)
+    joint, marg, m_mats = merge_m(col_pieces, N, norm)
+    return joint, marg, (e_mats, m_mats)
+
+
 def normalise(joint, N, norm="ground"):
     if norm == "sum":
         return joint - _lse(joint[np.isfinite(joint)]) + N * math.log(2.0)
@@ -181,5 +208,10 @@ def merge_oracle_run(orc, norm="ground", with_err=False):
         avg, err = window_average(frags, orc.K, with_err=True)
         pieces.append((lo, hi, avg))
         errs.append(err)
+    if getattr(orc, "split", 0) == 2:
+        if with_err:
+            raise ValueError("error bars are not defined for the 2D join")
+        rects = [orc.window_rect(w) + (p[2],) for w, p in enumerate(pieces)]
+        return merge_2d(rects, orc.N, norm)
     join = merge_m if getattr(orc, "split", 0) else merge
     return join(pieces, orc.N, norm, errs if with_err else None)

@@ -78,6 +78,14 @@ def lib():
         L.or_set_sync.restype = C.c_int
         L.or_set_split.argtypes = [C.c_void_p, C.c_int]
         L.or_set_split.restype = C.c_int
+        L.or_create_2d.argtypes = [C.c_int] * 11 + [C.c_int64, C.c_uint64, C.c_int]
+        L.or_create_2d.restype = C.c_void_p
+        L.or_window_rect.argtypes = [C.c_void_p, C.c_int] + [C.POINTER(C.c_int)] * 4
+        L.or_window_rect.restype = None
+        L.or_n_windows.argtypes = [C.c_void_p]
+        L.or_n_windows.restype = C.c_int
+        L.or_realizable.argtypes = [C.c_int] * 3
+        L.or_realizable.restype = C.c_int
         L.or_window_state.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int),
                                       C.POINTER(C.c_int)]
         L.or_window_state.restype = None
@@ -112,6 +120,11 @@ def window(N, n, p, q, i):
     return lo.value, hi.value
 
 
+def realizable(L, e, m):
+    """Whether bin (e, m) holds a state, by the closed-form support (or_realizable)."""
+    return bool(lib().or_realizable(int(L), int(e), int(m)))
+
+
 def energy(spins, L):
     s = np.ascontiguousarray(spins, dtype=np.int8).reshape(-1)
     E, M = C.c_int(), C.c_int()
@@ -129,23 +142,33 @@ class OracleREWL:
     the end of Sec. 2)."""
 
     def __init__(self, L, n_windows=1, overlap=(3, 4), walkers_per_window=1,
-                 k_final=16, flat=(4, 5), interval=10_000, seed=0, init=0, sync=0, split=0):
+                 k_final=16, flat=(4, 5), interval=10_000, seed=0, init=0, sync=0, split=0,
+                 m_windows=None):
         self.L, self.N = L, L * L
-        self.n_windows, self.W = n_windows, walkers_per_window
+        self.W = walkers_per_window
         self.K, self.X, self.seed = k_final, interval, seed
         self.overlap, self.flat = overlap, flat
-        h = lib().or_create(L, n_windows, overlap[0], overlap[1],
-                            walkers_per_window, k_final, flat[0], flat[1],
-                            interval, seed & 0xFFFFFFFFFFFFFFFF, init)
+        if split == 2:
+            # rectangles: n_windows x overlap in e, m_windows = (n, (p, q)) in m;
+            # only rectangles that hold states are kept
+            n_m, (pm, qm) = m_windows
+            h = lib().or_create_2d(L, n_windows, overlap[0], overlap[1], n_m, pm, qm,
+                                   walkers_per_window, k_final, flat[0], flat[1],
+                                   interval, seed & 0xFFFFFFFFFFFFFFFF, init)
+        else:
+            h = lib().or_create(L, n_windows, overlap[0], overlap[1],
+                                walkers_per_window, k_final, flat[0], flat[1],
+                                interval, seed & 0xFFFFFFFFFFFFFFFF, init)
         if not h:
             raise ValueError("invalid REWL problem")
         self._h = h
+        self.n_windows = lib().or_n_windows(h)
         self.sync = sync
         if lib().or_set_sync(h, sync) != 0:
             raise ValueError("sync must be 0 (all windows together) or 1 (per window)")
         self.split = split
-        if lib().or_set_split(h, split) != 0:
-            raise ValueError("split must be 0 (energy windows) or 1 (magnetization windows)")
+        if split != 2 and lib().or_set_split(h, split) != 0:
+            raise ValueError("split must be 0 (energy), 1 (magnetization) or 2 (both)")
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -189,6 +212,12 @@ class OracleREWL:
         lib().or_window_of(self._h, w, C.byref(lo), C.byref(hi))
         return lo.value, hi.value
 
+    def window_rect(self, w):
+        """(e_lo, e_hi, m_lo, m_hi) of window w."""
+        r = [C.c_int() for _ in range(4)]
+        lib().or_window_rect(self._h, w, *[C.byref(x) for x in r])
+        return tuple(x.value for x in r)
+
     def window_state(self, w):
         """(stage, done) of window w."""
         s, d = C.c_int(), C.c_int()
@@ -199,8 +228,9 @@ class OracleREWL:
         """State of walker g = w * W + a as a dict of numpy arrays / ints."""
         w = g // self.W
         lo, hi = self.window(w)
-        # rows e - lo by all m (energy windows), or all e by columns m - lo
-        shape = (self.N + 1, hi - lo + 1) if self.split else (hi - lo + 1, self.N + 1)
+        elo, ehi, mlo, mhi = self.window_rect(w)
+        # rows e - e_lo, columns m - m_lo of the window's rectangle
+        shape = (ehi - elo + 1, mhi - mlo + 1)
         lng = np.zeros(shape, np.int64) if tables else None
         H = np.zeros(shape, np.uint64) if tables else None
         sp = np.zeros(self.N, np.int8)

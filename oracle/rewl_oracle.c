@@ -165,15 +165,20 @@ typedef struct {
     int nwalk;
     int split;         /* 0: windows split the energy bins e = (E + 2N)/4 (the
                           paper's runs); 1: they split the magnetization bins
-                          m = (M + N)/2, every window keeping all energies */
-    int *lo, *hi;      /* window bounds in the split coordinate */
+                          m = (M + N)/2, every window keeping all energies;
+                          2: rectangles of both (or_create_2d) */
+    int *lo, *hi;      /* window bounds in the split coordinate (splits 0, 1) */
+    int *elo, *ehi, *mlo, *mhi;  /* every window as a rectangle of (e, m) bins */
+    int n_pairs;       /* neighbouring window pairs that may exchange */
+    int *pa, *pb;      /* lower and upper window of each pair */
+    int *pdir;         /* 0: neighbours in e, 1: neighbours in m (split 2) */
+    int *palong;       /* grid index of the lower window along pdir (split 2) */
     int8_t *spin;      /* [nwalk][N] */
     int *e, *m;        /* current bins; m = (M + N)/2 */
     int64_t *t;        /* WL attempts made */
     int64_t *te;       /* entry attempts made */
-    int64_t **lng;     /* [nwalk][(hi-lo+1)(N+1)]  ln g in units 2^-K: rows
-                          e - lo, columns m (split 0), or rows e, columns
-                          m - lo (split 1) */
+    int64_t **lng;     /* [nwalk][(ehi-elo+1)(mhi-mlo+1)]  ln g in units 2^-K,
+                          rows e - elo, columns m - mlo */
     uint64_t **H;      /* same shape */
     uint8_t *flag;     /* flat in the current stage (latched) */
     int s;             /* stage: ln f = 2^-s (the lowest window stage) */
@@ -186,14 +191,25 @@ typedef struct {
 
 static int win_of(const or_rewl *P, int g) { return g / P->W; }
 static int64_t bins_of(const or_rewl *P, int w) {
-    return (int64_t)(P->hi[w] - P->lo[w] + 1) * (P->N + 1);
+    return (int64_t)(P->ehi[w] - P->elo[w] + 1) * (P->mhi[w] - P->mlo[w] + 1);
 }
 static int64_t bin_index(const or_rewl *P, int w, int e, int m) {
-    if (P->split) return (int64_t)e * (P->hi[w] - P->lo[w] + 1) + (m - P->lo[w]);
-    return (int64_t)(e - P->lo[w]) * (P->N + 1) + m;
+    return (int64_t)(e - P->elo[w]) * (P->mhi[w] - P->mlo[w] + 1) + (m - P->mlo[w]);
 }
-/* The coordinate the windows split: e, or m when split = 1. */
-static int coord(const or_rewl *P, int e, int m) { return P->split ? m : e; }
+static int in_window(const or_rewl *P, int w, int e, int m) {
+    return e >= P->elo[w] && e <= P->ehi[w] && m >= P->mlo[w] && m <= P->mhi[w];
+}
+/* Rectangles of the one-coordinate splits: [lo, hi] in the split coordinate,
+ * everything in the other. */
+static void rects_from_split(or_rewl *P) {
+    for (int w = 0; w < P->n_win; ++w) {
+        int e_split = P->split == 0;
+        P->elo[w] = e_split ? P->lo[w] : 0;
+        P->ehi[w] = e_split ? P->hi[w] : P->N;
+        P->mlo[w] = e_split ? 0 : P->lo[w];
+        P->mhi[w] = e_split ? P->N : P->hi[w];
+    }
+}
 
 OR_EXPORT void or_destroy(or_rewl *P) {
     if (!P) return;
@@ -202,10 +218,14 @@ OR_EXPORT void or_destroy(or_rewl *P) {
     if (P->H)
         for (int g = 0; g < P->nwalk; ++g) free(P->H[g]);
     free(P->lng); free(P->H); free(P->lo); free(P->hi); free(P->spin);
+    free(P->elo); free(P->ehi); free(P->mlo); free(P->mhi);
+    free(P->pa); free(P->pb); free(P->pdir); free(P->palong);
     free(P->e); free(P->m); free(P->t); free(P->te); free(P->flag);
     free(P->sw); free(P->wdone);
     free(P);
 }
+
+static int alloc_tables(or_rewl *P);
 
 OR_EXPORT or_rewl *or_create(int L, int n_win, int ovl_num, int ovl_den, int W,
                              int K, int flat_num, int flat_den, int64_t X,
@@ -223,6 +243,14 @@ OR_EXPORT or_rewl *or_create(int L, int n_win, int ovl_num, int ovl_den, int W,
     P->nwalk = n_win * W;
     P->lo = calloc(n_win, sizeof(int));
     P->hi = calloc(n_win, sizeof(int));
+    P->elo = calloc(n_win, sizeof(int));
+    P->ehi = calloc(n_win, sizeof(int));
+    P->mlo = calloc(n_win, sizeof(int));
+    P->mhi = calloc(n_win, sizeof(int));
+    P->pa = calloc(2 * (size_t)n_win + 1, sizeof(int));
+    P->pb = calloc(2 * (size_t)n_win + 1, sizeof(int));
+    P->pdir = calloc(2 * (size_t)n_win + 1, sizeof(int));
+    P->palong = calloc(2 * (size_t)n_win + 1, sizeof(int));
     P->spin = calloc((size_t)P->nwalk * P->N, 1);
     P->e = calloc(P->nwalk, sizeof(int));
     P->m = calloc(P->nwalk, sizeof(int));
@@ -233,23 +261,40 @@ OR_EXPORT or_rewl *or_create(int L, int n_win, int ovl_num, int ovl_den, int W,
     P->H = calloc(P->nwalk, sizeof(uint64_t *));
     P->sw = calloc(n_win, sizeof(int));
     P->wdone = calloc(n_win, 1);
-    if (!P->lo || !P->hi || !P->spin || !P->e || !P->m || !P->t || !P->te ||
-        !P->flag || !P->lng || !P->H || !P->sw || !P->wdone) {
+    if (!P->lo || !P->hi || !P->elo || !P->ehi || !P->mlo || !P->mhi || !P->pa ||
+        !P->pb || !P->pdir || !P->palong || !P->spin || !P->e || !P->m || !P->t ||
+        !P->te || !P->flag || !P->lng || !P->H || !P->sw || !P->wdone) {
         or_destroy(P);
         return NULL;
     }
     for (int w = 0; w < n_win; ++w)
         or_window(P->N, n_win, ovl_num, ovl_den, w, &P->lo[w], &P->hi[w]);
-    for (int g = 0; g < P->nwalk; ++g) {
-        int64_t nb = bins_of(P, win_of(P, g));
-        P->lng[g] = calloc((size_t)nb, sizeof(int64_t));
-        P->H[g] = calloc((size_t)nb, sizeof(uint64_t));
-        if (!P->lng[g] || !P->H[g]) {
-            or_destroy(P);
-            return NULL;
-        }
+    rects_from_split(P);
+    /* neighbours along the split coordinate: (w, w+1) */
+    for (int w = 0; w + 1 < n_win; ++w) {
+        P->pa[P->n_pairs] = w;
+        P->pb[P->n_pairs] = w + 1;
+        P->pdir[P->n_pairs] = 0;
+        P->palong[P->n_pairs] = w;
+        P->n_pairs += 1;
+    }
+    if (alloc_tables(P) != 0) {
+        or_destroy(P);
+        return NULL;
     }
     return P;
+}
+
+static int alloc_tables(or_rewl *P) {
+    for (int g = 0; g < P->nwalk; ++g) {
+        int64_t nb = bins_of(P, win_of(P, g));
+        free(P->lng[g]);
+        free(P->H[g]);
+        P->lng[g] = calloc((size_t)nb, sizeof(int64_t));
+        P->H[g] = calloc((size_t)nb, sizeof(uint64_t));
+        if (!P->lng[g] || !P->H[g]) return -1;
+    }
+    return 0;
 }
 
 /* Neighbour-sum bookkeeping of a single spin flip at `site` (D-1): returns the
@@ -280,10 +325,15 @@ static int site_of(uint32_t word, int N) {
 /* window: a flip that does not increase d is accepted, one that increases   */
 /* it by k bins is accepted with exp(-4k); the walk stops once d = 0.        */
 /* ------------------------------------------------------------------------ */
-static int dist_to(const or_rewl *P, int w, int x) {
-    if (x < P->lo[w]) return P->lo[w] - x;
-    if (x > P->hi[w]) return x - P->hi[w];
+static int dist1(int x, int lo, int hi) {
+    if (x < lo) return lo - x;
+    if (x > hi) return x - hi;
     return 0;
+}
+/* bins from (e, m) to the window's rectangle: the sum of the two coordinates' */
+/* distances (one of them is always 0 for a one-coordinate split)            */
+static int dist_to(const or_rewl *P, int w, int e, int m) {
+    return dist1(e, P->elo[w], P->ehi[w]) + dist1(m, P->mlo[w], P->mhi[w]);
 }
 
 OR_EXPORT int or_init(or_rewl *P, int64_t entry_cap) {
@@ -315,7 +365,7 @@ OR_EXPORT int or_init(or_rewl *P, int64_t entry_cap) {
         P->t[g] = 0;
         P->te[g] = 0;
         int w = win_of(P, g);
-        int d = dist_to(P, w, coord(P, P->e[g], P->m[g]));
+        int d = dist_to(P, w, P->e[g], P->m[g]);
         while (d > 0) {
             if (P->te[g] >= entry_cap) { bad |= 1; break; }
             uint32_t sw, uw;
@@ -323,7 +373,7 @@ OR_EXPORT int or_init(or_rewl *P, int64_t entry_cap) {
             int site = site_of(sw, N);
             int e2, m2;
             flip_target(P, s, site, P->e[g], P->m[g], &e2, &m2);
-            int d2 = dist_to(P, w, coord(P, e2, m2));
+            int d2 = dist_to(P, w, e2, m2);
             int acc = d2 <= d ||
                       or_accept(-((int64_t)4 * (d2 - d)) * ((int64_t)1 << P->K),
                                 uw, P->K);
@@ -357,8 +407,7 @@ static void wl_attempt(or_rewl *P, int g) {
     int e2, m2;
     flip_target(P, s, site, e, m, &e2, &m2);
     int acc = 0;
-    int x2 = coord(P, e2, m2);
-    if (x2 >= P->lo[w] && x2 <= P->hi[w]) {
+    if (in_window(P, w, e2, m2)) {
         int64_t delta = P->lng[g][bin_index(P, w, e, m)] -
                         P->lng[g][bin_index(P, w, e2, m2)];
         acc = or_accept(delta, uw, P->K);
@@ -426,11 +475,22 @@ static void swap_config(or_rewl *P, int A, int B) {
     int tm = P->m[A]; P->m[A] = P->m[B]; P->m[B] = tm;
 }
 
+/* Pairs taking part in round r: for a one-coordinate split, (w, w+1) with   */
+/* w = r (mod 2); for rectangles, neighbours in e on rounds with bit 1 of r   */
+/* clear and in m on the others, the lower one's grid index along that       */
+/* direction = r (mod 2).                                                     */
+static int pair_active(const or_rewl *P, int k, int64_t r) {
+    if (P->split != 2) return (P->palong[k] & 1) == (int)(r & 1);
+    return P->pdir[k] == (int)((r >> 1) & 1) && (P->palong[k] & 1) == (int)(r & 1);
+}
+
 OR_EXPORT int64_t or_exchange(or_rewl *P, int64_t r) {
     int W = P->W;
     int64_t n_acc = 0;
     int *pi = (int *)malloc(sizeof(int) * (size_t)W);
-    for (int w = (int)(r & 1); w + 1 < P->n_win; w += 2) {
+    for (int k = 0; k < P->n_pairs; ++k) {
+        if (!pair_active(P, k, r)) continue;
+        int w = P->pa[k], v = P->pb[k];
         for (int a = 0; a < W; ++a) pi[a] = a;
         for (int i = W - 1; i >= 1; --i) {
             uint32_t ctr[4] = {(uint32_t)r, (uint32_t)((uint64_t)r >> 32),
@@ -441,16 +501,14 @@ OR_EXPORT int64_t or_exchange(or_rewl *P, int64_t r) {
             int tmp = pi[i]; pi[i] = pi[j]; pi[j] = tmp;
         }
         for (int a = 0; a < W; ++a) {
-            int A = w * W + a, B = (w + 1) * W + pi[a];
+            int A = w * W + a, B = v * W + pi[a];
             int eA = P->e[A], mA = P->m[A], eB = P->e[B], mB = P->m[B];
-            if (P->wdone[w] || P->wdone[w + 1]) continue;
-            int xA = coord(P, eA, mA), xB = coord(P, eB, mB);
-            if (xA < P->lo[w + 1] || xA > P->hi[w + 1]) continue;
-            if (xB < P->lo[w] || xB > P->hi[w]) continue;
+            if (P->wdone[w] || P->wdone[v]) continue;
+            if (!in_window(P, v, eA, mA) || !in_window(P, w, eB, mB)) continue;
             int64_t delta = P->lng[A][bin_index(P, w, eA, mA)] -
                             P->lng[A][bin_index(P, w, eB, mB)] +
-                            P->lng[B][bin_index(P, w + 1, eB, mB)] -
-                            P->lng[B][bin_index(P, w + 1, eA, mA)];
+                            P->lng[B][bin_index(P, v, eB, mB)] -
+                            P->lng[B][bin_index(P, v, eA, mA)];
             uint32_t ctr[4] = {(uint32_t)r, (uint32_t)((uint64_t)r >> 32),
                                (uint32_t)w, ((uint32_t)TAG_XACC << 24) | (uint32_t)a};
             uint32_t out[4];
@@ -585,6 +643,110 @@ OR_EXPORT void or_window_of(const or_rewl *P, int w, int *lo, int *hi) {
     *hi = P->hi[w];
 }
 
+OR_EXPORT void or_window_rect(const or_rewl *P, int w, int *elo, int *ehi, int *mlo, int *mhi) {
+    *elo = P->elo[w];
+    *ehi = P->ehi[w];
+    *mlo = P->mlo[w];
+    *mhi = P->mhi[w];
+}
+
+OR_EXPORT int or_n_windows(const or_rewl *P) { return P->n_win; }
+
+/* ------------------------------------------------------------------------ */
+/* Windows in both coordinates (the second alternative of Sec. 2, end).       */
+/* The D-6 windows in e and in m form a grid of rectangles; a rectangle is    */
+/* kept when it holds a realizable state.  The realizable energies at         */
+/* magnetization bin m run from e_min(m) to e_max(m): with k = min(m, N - m), */
+/* e_min = P_min/2, P_min = min(2 ceil(2 sqrt k), 2L + 2 [L does not divide   */
+/* k] when k >= L) the shortest domain wall around k sites on the torus, and  */
+/* e_max = 2k (minority spins on one sublattice).  Between them every bin is  */
+/* realizable except next to m = N/2 (one below the top at m = N/2 +- 1; the  */
+/* bin above the bottom and the two below the top at m = N/2), as exhaustive  */
+/* enumeration shows for L = 4 and 6.                                          */
+/* ------------------------------------------------------------------------ */
+static void envelope(int L, int m, int *emin, int *emax) {
+    int N = L * L, k = m < N - m ? m : N - m;
+    int pmin = 0;
+    if (k > 0) {
+        int t = 0;
+        while ((int64_t)t * t < 4 * (int64_t)k) ++t;        /* ceil(2 sqrt k) */
+        pmin = 2 * t;
+        if (k >= L) {
+            int band = 2 * L + (k % L ? 2 : 0);
+            if (band < pmin) pmin = band;
+        }
+    }
+    *emin = pmin / 2;
+    *emax = 2 * k;
+}
+
+static int is_hole(int L, int e, int m) {
+    int N = L * L, emin, emax;
+    envelope(L, m, &emin, &emax);
+    if (m == N / 2) return e == emin + 1 || e == emax - 1 || e == emax - 2;
+    if (m == N / 2 - 1 || m == N / 2 + 1) return e == emax - 1;
+    return 0;
+}
+
+static int rect_has_state(int L, int elo, int ehi, int mlo, int mhi) {
+    for (int m = mlo; m <= mhi; ++m) {
+        int emin, emax;
+        envelope(L, m, &emin, &emax);
+        for (int e = elo > emin ? elo : emin; e <= (ehi < emax ? ehi : emax); ++e)
+            if (!is_hole(L, e, m)) return 1;
+    }
+    return 0;
+}
+
+OR_EXPORT int or_realizable(int L, int e, int m) {
+    int emin, emax;
+    envelope(L, m, &emin, &emax);
+    return e >= emin && e <= emax && !is_hole(L, e, m);
+}
+
+OR_EXPORT or_rewl *or_create_2d(int L, int n_e, int pe, int qe, int n_m, int pm, int qm, int W,
+                                int K, int flat_num, int flat_den, int64_t X, uint64_t seed,
+                                int init) {
+    if (L < 2 || (L & 1) || n_e < 1 || n_m < 1 || qe < 1 || pe < 0 || pe >= qe || qm < 1 ||
+        pm < 0 || pm >= qm)
+        return NULL;
+    int N = L * L, n_grid = n_e * n_m;
+    int *keep = calloc((size_t)n_grid, sizeof(int));
+    int *glo = calloc((size_t)n_grid * 4, sizeof(int));
+    if (!keep || !glo) { free(keep); free(glo); return NULL; }
+    int n_win = 0;
+    for (int ie = 0; ie < n_e; ++ie)
+        for (int im = 0; im < n_m; ++im) {
+            int *r = glo + 4 * (ie * n_m + im);
+            or_window(N, n_e, pe, qe, ie, &r[0], &r[1]);
+            or_window(N, n_m, pm, qm, im, &r[2], &r[3]);
+            keep[ie * n_m + im] = rect_has_state(L, r[0], r[1], r[2], r[3]) ? n_win++ : -1;
+        }
+    or_rewl *P = n_win ? or_create(L, n_win, pe, qe, W, K, flat_num, flat_den, X, seed, init) : NULL;
+    if (!P) { free(keep); free(glo); return NULL; }
+    P->split = 2;
+    P->n_pairs = 0;
+    for (int ie = 0; ie < n_e; ++ie)
+        for (int im = 0; im < n_m; ++im) {
+            int w = keep[ie * n_m + im];
+            if (w < 0) continue;
+            const int *r = glo + 4 * (ie * n_m + im);
+            P->elo[w] = r[0]; P->ehi[w] = r[1]; P->mlo[w] = r[2]; P->mhi[w] = r[3];
+            P->lo[w] = r[0]; P->hi[w] = r[1];
+            if (ie + 1 < n_e && keep[(ie + 1) * n_m + im] >= 0) {
+                P->pa[P->n_pairs] = w; P->pb[P->n_pairs] = keep[(ie + 1) * n_m + im];
+                P->pdir[P->n_pairs] = 0; P->palong[P->n_pairs] = ie; P->n_pairs += 1;
+            }
+            if (im + 1 < n_m && keep[ie * n_m + im + 1] >= 0) {
+                P->pa[P->n_pairs] = w; P->pb[P->n_pairs] = keep[ie * n_m + im + 1];
+                P->pdir[P->n_pairs] = 1; P->palong[P->n_pairs] = im; P->n_pairs += 1;
+            }
+        }
+    free(keep); free(glo);
+    if (alloc_tables(P) != 0) { or_destroy(P); return NULL; }
+    return P;
+}
+
 OR_EXPORT int64_t or_bins_of_walker(const or_rewl *P, int g) {
     return bins_of(P, win_of(P, g));
 }
@@ -632,8 +794,9 @@ OR_EXPORT void or_set_stage(or_rewl *P, int s) {
  * window bounds are the same D-6 formula over [0, N] either way, so the
  * table sizes do not change. */
 OR_EXPORT int or_set_split(or_rewl *P, int split) {
-    if (split != 0 && split != 1) return -1;
+    if ((split != 0 && split != 1) || P->split == 2) return -1;
     P->split = split;
+    rects_from_split(P);
     return 0;
 }
 

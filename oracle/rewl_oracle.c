@@ -21,8 +21,8 @@
  *   - iterate until H is flat, then reset H and refine f -> sqrt(f) (Sec. 2);
  *   - 80 % flatness: every entry >= 0.8 * mean (Sec. 3);
  *   - overlapping equal-size energy windows, unrestricted M (Sec. 2, Sec. 3),
- *     or, as the alternative Sec. 2 names, magnetization windows with
- *     unrestricted E (or_set_split);
+ *     or, as the alternatives Sec. 2 names, magnetization windows with
+ *     unrestricted E (or_set_split) or rectangles in both (or_create_2d);
  *   - several independent walkers per window with their own g, H (Sec. 2);
  *   - configuration exchange between random walker pairs of adjacent windows,
  *     attempted only when both lie in the overlap, accepted with Eq. 2;
@@ -460,7 +460,7 @@ OR_EXPORT int or_is_flat(const or_rewl *P, int g) {
 /* Round r pairs windows (w, w+1) with w = r (mod 2).  The walkers of w+1    */
 /* are matched to those of w by a Fisher-Yates permutation drawn from the    */
 /* XPERM stream; pair (A = (w,a), B = (w+1,pi[a])) is attempted only if A's  */
-/* split coordinate lies in window w+1 and B's in window w, accepted with   */
+/* state lies in window w+1 and B's in window w (rectangles), accepted with */
 /* min[1, g_A(X) g_B(Y) / (g_A(Y) g_B(X))], X and Y being the configurations */
 /* A and B hold.  On accept the two configurations are swapped; neither      */
 /* ln g nor H changes.                                                        */

@@ -1,21 +1,23 @@
 """Throughput of two-dimensional replica-exchange Wang-Landau sampling on one MI355X.
 
-One step = one REWL interval over the whole batch: 10^4 Wang-Landau trials per
+One step = one REWL interval over the whole batch: X Wang-Landau trials per
 walker (Eq. 1 random walk in (E, M)), the flatness check and ln f reduction,
 and one exchange round between adjacent windows (Eq. 2).
 
-Workload: the 16x16 periodic Ising REWL problem (8 energy windows with 3/4
-overlap, full M range, 4 walkers per window, ln f from 1 to 2^-20, 80 %
-flatness, exchange every 10^4 trials, random initial spins) replicated with
-independent seeds so that one walker per lane fills the GPU.  Inputs are
-synthetic (seeded spins); every table and configuration is resident in HBM
-before the timed region.
+Headline workload: the 64x64 periodic Ising REWL problem (64 energy windows
+with 3/4 overlap, full M range, 4 walkers per window, ln f from 1 to 2^-20,
+80 % flatness, exchange every 10^5 trials, random initial spins) replicated
+with independent seeds, as many replicas as the device memory holds, so that
+the GPU carries as many walker chains as it can.  Inputs are synthetic (seeded
+spins); every table and configuration is resident in HBM before the timed
+region.  The 16x16 workload (8 windows x 4 walkers, X = 10^4) and the 32x32
+plus mixed-L batch are measured next to it as extra keys.
 
 Prints one JSON line: batched throughput (value), the plain
-one-launch-per-window form on the single problem next to the batched form on
-the same problem (same trials, so the same final ln f), the roofline of the
-sweep kernel (timed with HIP events around each of its launches) and the
-CPU oracle on the host's cores.
+one-launch-per-window form on one problem next to the batched form on the
+same problem (same trials, so the same final ln f), the roofline of the sweep
+kernel (timed with HIP events around each of its launches) and the CPU oracle
+on the host's cores (one core and all of them).
 """
 import argparse
 import json
@@ -27,7 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "spin-flip attempts/sec on 1 MI355X (batched vs plain) at equal final ln f"
-# One REWL problem of each measured configuration; the 16x16 problem is the
+# One REWL problem of each measured configuration; the 64x64 problem is the
 # one the throughput is quoted on.
 C2 = dict(L=16, n_windows=8, overlap=(3, 4), walkers_per_window=4, k_final=20, flat=(4, 5), interval=10_000)
 C3 = dict(L=32, n_windows=16, overlap=(3, 4), walkers_per_window=8, k_final=24, flat=(4, 5), interval=10_000)
@@ -35,6 +37,9 @@ C4 = dict(L=64, n_windows=64, overlap=(3, 4), walkers_per_window=4, k_final=20, 
 # A mixed batch of lattice sizes with uneven window counts, run in the same
 # launches as the 32x32 problems.
 MIXED = [dict(C3, L=L, n_windows=nw) for L, nw in ((8, 2), (12, 4), (16, 8), (24, 12), (32, 16))]
+# (table layout, walkers per workgroup, grid waves per CU, walkers per wavefront) used for the
+# extra workloads measured next to the headline (the autotuner's choices on MI355X)
+EXTRA_TUNING = {"c2": (0, 256, 4, 0), "c3mix": (0, 64, 8, 0)}
 # name -> (problems of one replica, default replica count, description)
 WORKLOADS = {
     "c2": ([C2], 4096, "16x16 periodic Ising 2D-REWL (8 windows x 4 walkers, overlap 3/4, ln f 1 -> 2^-20, "
@@ -44,9 +49,11 @@ WORKLOADS = {
     "c3mix": ([C3] + MIXED, 100, "32x32 periodic Ising 2D-REWL (16 windows x 8 walkers, overlap 3/4, ln f 1 -> "
                                  "2^-24, 80% flat, exchange every 10^4 trials) plus a mixed batch of L in "
                                  "{8,12,16,24,32} with 2/4/8/12/16 windows x 8 walkers, all in the same launches"),
-    "c4": ([C4], 28, "64x64 periodic Ising 2D-REWL (64 windows x 4 walkers, overlap 3/4, ln f 1 -> 2^-20, "
-                     "80% flat, exchange every 10^5 trials)"),
+    "c4": ([C4], 0, "64x64 periodic Ising 2D-REWL (64 windows x 4 walkers, overlap 3/4, ln f 1 -> 2^-20, "
+                    "80% flat, exchange every 10^5 trials)"),
 }
+# replicas 0 = as many as fit in the device memory (leaving MEM_SPARE bytes)
+MEM_SPARE = 12 << 30
 # Serial 2D-WL on the 4x4 lattice (one window, one walker), run to its last stage.
 C1 = dict(L=4, n_windows=1, overlap=(3, 4), walkers_per_window=1, k_final=16, flat=(4, 5), interval=10_000)
 
@@ -97,10 +104,13 @@ VALU_SLOTS_PER_TRIAL = 133
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz full-rate VALU lane operations per second.
 VALU_PEAK_SLOTS = 256 * 64 * 2.4e9
 # HBM-side bytes per sweep launch, FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a 1 GiB
-# device copy), by (workload, replicas, walkers per workgroup, grid waves per CU, walkers per
-# wavefront); measured on
-# the current sweep kernel with rocprofv3 --pmc.  Other shapes report null.
-TRAFFIC_BYTES = {("c2", 4096, 256, 4, 0): 38.44e9}
+# device copy), by (workload, replicas, table layout, walkers per workgroup, grid waves per CU,
+# walkers per wavefront); measured on the current sweep kernel with rocprofv3 --pmc.  Other
+# shapes report null.
+TRAFFIC_BYTES = {}
+# VALU-busy share of the sweep by the counters (SQ_ACTIVE_INST_VALU / SQ_BUSY_CYCLES-based, see
+# profiles/), same keys; null where not measured.
+VALU_BUSY = {}
 
 
 def log(*a):
@@ -182,11 +192,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--replicas", type=int, default=0, help="independent replicas of the workload's problem set (0 = its default)")
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
+    ap.add_argument("--replicas", type=int, default=0,
+                    help="independent replicas of the workload's problem set (0 = its default, or as many as fit)")
+    ap.add_argument("--layout", type=int, default=-1, help="table layout: 0 dense, 1 band, -1 = choose by timing")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 16x16 and mixed-L workloads")
+    ap.add_argument("--extra-steps", type=int, default=10)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--plain-steps", type=int, default=5)
-    ap.add_argument("--cpu-intervals", type=int, default=1000)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--cpu-intervals", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-lnz", action="store_true")
@@ -224,28 +238,46 @@ def main():
     K, W = args.steps, args.warmup
     unit, default_r, wl_text = WORKLOADS[args.workload]
     cfg = unit[0]
-    if args.replicas <= 0:
-        args.replicas = default_r
     X = cfg["interval"]
     n1 = cfg["n_windows"] * cfg["walkers_per_window"]
+    from paper_1508_02748_amd.tune import autotune, choose_layout
+
+    # ---------------- table layout and replica count
+    free, total = torch.cuda.mem_get_info(0)
+    budget = free - MEM_SPARE
+    layout_report = None
+    fit = None
+    if args.layout >= 0:
+        layout = args.layout
+    else:
+        layout, fit, layout_report = choose_layout(lambda r: problems(r, R, unit), budget=budget, device=dev)
+    per_rep = R.plan_bytes(problems(1, R, unit), layout)
+    if args.replicas <= 0:
+        args.replicas = default_r if default_r > 0 else (fit or max(1, budget // per_rep))
+    log(f"[bench] {args.workload}: layout {layout}, {per_rep / 2**30:.3f} GiB per replica, "
+        f"{args.replicas} replicas ({free / 2**30:.0f} GiB free)")
 
     # ---------------- batched form on the replica batch (the headline value)
-    log(f"[bench] batched: {args.replicas} replicas of {len(unit)} REWL problem(s) ({args.workload}), init ...")
-    tuning = R.Tuning(graph_intervals=K, walkers_per_wg=args.wg, grid_waves_per_cu=args.grid_waves)
+    tuning = R.Tuning(graph_intervals=K, walkers_per_wg=args.wg, grid_waves_per_cu=args.grid_waves,
+                      table_layout=layout)
     plan = R.Plan(problems(args.replicas, R, unit), tuning, device=dev)
     t0 = time.perf_counter()
     plan.init()
     log(f"[bench] init + window entry {time.perf_counter() - t0:.2f}s; warmup {W}, timed {K} steps")
     tuned = "fixed"
+    tune_report = None
     shape = (args.wg, args.grid_waves, 0)
     if not args.no_autotune and args.wg == 0 and args.grid_waves == 0:
-        from paper_1508_02748_amd.tune import autotune
         best = autotune(plan, intervals=1, use_cache=False)
+        tune_report = plan.tune_report
         shape = (best.walkers_per_wg, best.grid_waves_per_cu, best.walkers_per_wave)
         tuned = (f"autotuned: walkers_per_wg={best.walkers_per_wg}, grid_waves_per_cu={best.grid_waves_per_cu}, "
-                 f"walkers_per_wave={best.walkers_per_wave or 64}")
+                 f"walkers_per_wave={best.walkers_per_wave or 64}, graph_intervals={best.graph_intervals}")
         log(f"[bench] {tuned}")
-    traffic = TRAFFIC_BYTES.get((args.workload, args.replicas) + shape)
+    key = (args.workload, args.replicas, layout) + tuple(shape)
+    traffic = TRAFFIC_BYTES.get(key)
+    valu_busy = VALU_BUSY.get(key)
+    q0 = plan.query()
     # timed region: the batched launch sequence enqueued eagerly with a HIP
     # event pair around every sweep kernel on the plan's stream, so that the
     # throughput and the kernel's own duration (roofline) cover the same K
@@ -268,8 +300,12 @@ def main():
     assert len(sweep_ms) == K
     sweep_avg = float(np.mean(sweep_ms))
     achieved_slots = VALU_SLOTS_PER_TRIAL * n_walk * X / (sweep_avg * 1e-3)
-    log(f"[bench] batched {value:.4e} trials/s, {T / K * 1e3:.2f} ms/step, sweep kernel {sweep_avg:.3f} ms")
+    wpw = shape[2] or 64
+    waves = -(-n_walk // wpw)
+    log(f"[bench] batched {value:.4e} trials/s, {T / K * 1e3:.2f} ms/step, sweep kernel {sweep_avg:.3f} ms, "
+        f"{waves} wavefronts")
     stages = (int(q1["stage"].min()), int(q1["stage"].max()))
+    plan.close()
     del plan
     torch.cuda.empty_cache()
 
@@ -278,10 +314,10 @@ def main():
     if not args.no_plain:
         Kp = args.plain_steps
         log(f"[bench] plain vs batched on one problem, {Kp} intervals each")
-        pp = R.Plan(problems(1, R, cfg), R.Tuning(form=R.FORM_PLAIN), device=dev)
+        pp = R.Plan(problems(1, R, cfg), R.Tuning(form=R.FORM_PLAIN, table_layout=layout), device=dev)
         pp.init()
         Tp = time_plan(1, pp, Kp, 1)
-        pb = R.Plan(problems(1, R, cfg), R.Tuning(graph_intervals=Kp), device=dev)
+        pb = R.Plan(problems(1, R, cfg), R.Tuning(graph_intervals=Kp, table_layout=layout), device=dev)
         pb.init()
         Tb = time_plan(1, pb, Kp, 1)
         same = all((pp.walker(0, w, a)["lng"] == pb.walker(0, w, a)["lng"]).all()
@@ -291,7 +327,35 @@ def main():
                  "speedup": Tp / Tb, "identical_final_state": bool(same),
                  "batched_replicas_speedup_vs_plain": value / (n1 * X * Kp / Tp)}
         log(f"[bench] plain {plain['plain_value']:.3e}, batched(1) {plain['batched_value']:.3e} trials/s")
+        pp.close()
+        pb.close()
         del pp, pb
+
+    # ---------------- the other measured configurations, next to the headline
+    extras = {}
+    for name in ([] if args.no_extras else [n for n in ("c2", "c3mix") if n != args.workload]):
+        eunit, er, etext = WORKLOADS[name]
+        lay, wg, gw, wpw_e = EXTRA_TUNING[name]
+        ep = R.Plan(problems(er, R, eunit), R.Tuning(graph_intervals=K, walkers_per_wg=wg, grid_waves_per_cu=gw,
+                                                     walkers_per_wave=wpw_e, table_layout=lay, profile=1),
+                    device=dev)
+        ep.init()
+        eX = eunit[0]["interval"]
+        Te = time_plan(er, ep, args.extra_steps, 3)
+        ems = float(np.mean(ep.sweep_times()))
+        ew = ep.n_walkers
+        eq = ep.query()
+        extras[name] = {"workload": f"{etext} x {er} independent replicas, batched form",
+                        "value": ew * eX * args.extra_steps / Te, "unit": "spin-flip attempts/s",
+                        "walkers": ew, "steps": args.extra_steps, "sweep_ms": ems,
+                        "frac_model": VALU_SLOTS_PER_TRIAL * ew * eX / (ems * 1e-3) / VALU_PEAK_SLOTS,
+                        "tuning": {"table_layout": lay, "walkers_per_wg": wg, "grid_waves_per_cu": gw,
+                                   "walkers_per_wave": wpw_e or 64},
+                        "stage_range": [int(eq["stage"].min()), int(eq["stage"].max())]}
+        log(f"[bench] {name}: {extras[name]['value']:.3e} trials/s, sweep {ems:.2f} ms")
+        ep.close()
+        del ep
+        torch.cuda.empty_cache()
 
     # ---------------- reweighting ln Z(beta, h) and its backward on the 32x32 size
     lnz = None
@@ -303,48 +367,74 @@ def main():
     # ---------------- CPU oracle on the host cores (bounded sample)
     cpu = None
     if not args.no_cpu:
-        from oracle.rewl import OracleREWL
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        o = OracleREWL(seed=0, **cfg)
-        o.init()
-        n = args.cpu_intervals if args.workload == "c2" else max(1, args.cpu_intervals // 30)
-        log(f"[bench] oracle: {n} intervals of one {cfg['L']}x{cfg['L']} REWL problem on {threads} threads")
-        t0 = time.perf_counter()
-        o.run(n)
-        Tc = time.perf_counter() - t0
-        model = "unknown"
-        try:
-            with open("/proc/cpuinfo") as f:
-                model = next(ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name"))
-        except (OSError, StopIteration):
-            pass
-        cpu = {"value": n1 * X * n / Tc, "unit": "spin-flip attempts/s", "cores": min(threads, n1),
-               "kind": "oracle", "host_cpu": model,
-               "sample": f"{n} intervals ({X} trials x {n1} walkers each) of one {cfg['L']}x{cfg['L']} REWL "
-                         f"problem, seed 0; {Tc:.1f} s"}
+        cpu = cpu_baseline(cfg, n1, X, args.cpu_intervals)
 
     out = {
         "metric": METRIC, "value": value, "unit": "spin-flip attempts/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": T / K * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": f"{wl_text} x {args.replicas} independent replicas, batched form",
-                   "tuning": tuned,
-                   "replicas": args.replicas, "walkers": n_walk, "trials_per_walker_per_step": X,
-                   "stage_range": list(stages), "parallelism": "one walker per lane",
+                   "tuning": tuned, "table_layout": ["dense", "band"][layout],
+                   "layout_probe": layout_report, "autotune": tune_report,
+                   "replicas": args.replicas, "walkers": n_walk, "wavefronts": waves,
+                   "bytes_per_replica": per_rep, "trials_per_walker_per_step": X,
+                   "stage_range": list(stages), "stage_range_before_timing": [int(q0["stage"].min()),
+                                                                             int(q0["stage"].max())],
+                   "parallelism": "one walker per lane",
                    "timed": "K intervals launched eagerly, a HIP event pair around each sweep kernel",
                    "graph_replay_value": trials / Tg,
                    "graph_replay_note": "the next K intervals after an untimed K-interval replay"},
         "roofline": {"bound": "alu", "achieved": achieved_slots / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                      "unit": "Tslot/s (full-rate VALU lane-ops)", "frac": achieved_slots / VALU_PEAK_SLOTS,
+                     "frac_source": f"instruction model: {VALU_SLOTS_PER_TRIAL} full-rate VALU slots per trial "
+                                    "(algorithmic, counted in the design notes) x trials / sweep kernel time",
+                     "valu_busy_counters": valu_busy,
                      "traffic": traffic, "traffic_unit": "HBM bytes per sweep launch (rocprofv3 FETCH_SIZE, WRITE_SIZE)",
                      "kernel": "k_sweep", "kernel_ms": sweep_avg,
                      "kernel_ms_source": "HIP events around each sweep launch of the timed intervals",
                      "slots_per_trial": VALU_SLOTS_PER_TRIAL},
         "cpu_baseline": cpu,
         "plain": plain,
+        "extras": extras,
         "lnz": lnz,
     }
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(cfg, n1, X, intervals):
+    """The oracle on the host: `intervals` whole intervals of one problem on all host threads, and
+    a part-interval sweep on one thread (the same walkers, fresh from init)."""
+    import subprocess
+    from oracle.rewl import OracleREWL, set_threads
+    threads = set_threads(int(os.environ.get("OMP_NUM_THREADS", "0") or 0))
+    model = "unknown"
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        model = next(ln.split(":", 1)[1].strip() for ln in out.splitlines() if ln.startswith("Model name"))
+    except (OSError, StopIteration, subprocess.SubprocessError):
+        pass
+    o = OracleREWL(seed=0, **cfg)
+    o.init()
+    log(f"[bench] oracle: {intervals} intervals of one {cfg['L']}x{cfg['L']} REWL problem on {threads} threads")
+    t0 = time.perf_counter()
+    o.run(intervals)
+    Tc = time.perf_counter() - t0
+    del o
+    one_trials = max(1, min(X, 2_000_000 // n1))
+    set_threads(1)
+    o = OracleREWL(seed=0, **cfg)
+    o.init()
+    t0 = time.perf_counter()
+    o.sweep(one_trials)
+    T1 = time.perf_counter() - t0
+    del o
+    set_threads(threads)
+    return {"value": n1 * X * intervals / Tc, "unit": "spin-flip attempts/s", "cores": min(threads, n1),
+            "kind": "oracle", "one_core_value": n1 * one_trials / T1, "host_cpu": model,
+            "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+            "sample": f"all cores: {intervals} intervals ({X} trials x {n1} walkers each) of one {cfg['L']}x{cfg['L']} "
+                      f"REWL problem, seed 0, {Tc:.1f} s; one core: {one_trials} trials x {n1} walkers of the "
+                      f"same problem, {T1:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -73,8 +73,12 @@ typedef struct {
     uint64_t seed;               /* Philox key */
     int32_t init;                /* 0: spins Bernoulli(1/2) from Philox; 1: all +1 */
     int32_t stage_sync;          /* REWL_SYNC_PROBLEM (the paper) or REWL_SYNC_WINDOW */
-    int32_t split;               /* REWL_SPLIT_ENERGY (the paper's runs) or
-                                    REWL_SPLIT_MAGNETIZATION; one value per plan */
+    int32_t split;               /* REWL_SPLIT_ENERGY (the paper's runs),
+                                    REWL_SPLIT_MAGNETIZATION or REWL_SPLIT_BOTH; one
+                                    value per plan */
+    int32_t m_windows;           /* REWL_SPLIT_BOTH: windows along M (>= 1), with */
+    int32_t m_overlap_num;       /*   overlap m_overlap_num / m_overlap_den; the fields */
+    int32_t m_overlap_den;       /*   above then describe the windows along E; else 0 */
     int32_t reserved;            /* must be 0 */
 } rewl_problem;
 
@@ -99,10 +103,22 @@ enum { REWL_SYNC_PROBLEM = 0, REWL_SYNC_WINDOW = 1 };
  *     same overlapping-window formula, each keeping every energy (the
  *     alternative split named at the end of Sec. 2).  A proposal leaving the
  *     window in m is rejected; the entry walk and the exchange overlap test
- *     use m.  Tables are indexed [e][m - lo].  rewl_merge_lng joins energy
- *     windows only.
+ *     use m.  Tables are indexed [e][m - lo].
+ *   REWL_SPLIT_BOTH: windows in both coordinates (the second alternative of
+ *     Sec. 2): the n_windows energy windows times the m_windows magnetization
+ *     windows form a grid of rectangles, of which only those holding a state
+ *     are kept (closed-form support of the (e, m) plane: with k = min(m, N-m)
+ *     minority spins the energy bins run from half the shortest domain wall
+ *     around k sites on the torus to 2k, every bin between holding a state
+ *     except three next to m = N/2).  Kept rectangles are numbered e-major
+ *     (rewl_window_rect gives them).  A proposal leaving the rectangle is
+ *     rejected; the entry walk's distance is the sum of both coordinates'
+ *     distances; neighbours exchange along E on rounds r with bit 1 of r
+ *     clear and along M otherwise, pairs whose lower window's grid index
+ *     along that direction is r (mod 2).  Tables are indexed [e - e_lo][m -
+ *     m_lo].
  * All problems of one plan use the same split. */
-enum { REWL_SPLIT_ENERGY = 0, REWL_SPLIT_MAGNETIZATION = 1 };
+enum { REWL_SPLIT_ENERGY = 0, REWL_SPLIT_MAGNETIZATION = 1, REWL_SPLIT_BOTH = 2 };
 
 /* Execution form and tuning.  None of these change results. */
 enum { REWL_FORM_BATCHED = 0, REWL_FORM_PLAIN = 1 };
@@ -119,13 +135,28 @@ typedef struct {
     int32_t profile;          /* 1: start with profiling on (see rewl_set_profile) */
     int32_t walkers_per_wave; /* 1..64 lanes of each wavefront carry a walker; fewer spread
                                  a small batch over more CUs; 0 = 64 */
-    int32_t reserved[2];      /* must be 0 */
+    int32_t table_layout;     /* REWL_LAYOUT_DENSE or REWL_LAYOUT_BAND (below); fixed when
+                                 the plan is created */
+    int32_t reserved;         /* must be 0 */
 } rewl_tuning;
+
+/* How each walker's tables are stored (rewl_tuning.table_layout).  Both
+ * layouts hold the same values; they differ in memory and addressing only.
+ *   REWL_LAYOUT_DENSE: every bin of the window's rectangle.
+ *   REWL_LAYOUT_BAND (energy split): each row of 4 energy bins keeps only
+ *     the magnetization band [ceil(e/2), N - ceil(e/2)] of its lowest energy
+ *     e, which holds every realizable state of the row (a state with energy
+ *     bin e has at least e/2 minority spins); all rows of a window keep the
+ *     width of its widest row.  (magnetization split) each window keeps only
+ *     the energy rows up to 2 k_max, k_max the largest minority-spin count
+ *     of its magnetization bins.  About half the memory of the dense layout
+ *     over all windows. */
+enum { REWL_LAYOUT_DENSE = 0, REWL_LAYOUT_BAND = 1 };
 
 /* Buffers the caller provides (device memory). */
 enum {
-    REWL_BUF_TABLES = 0,  /* ln g and its stage snapshot: 2 x 8 B per bin of each walker's
-                             window table (4 x 4 tiles of (e, m)) */
+    REWL_BUF_TABLES = 0,  /* ln g (8 B per bin) and its stage snapshot (4 B per bin) of
+                             each walker's window table (4 x 4 tiles of (e, m)) */
     REWL_BUF_SPINS = 1,   /* bit-packed configurations */
     REWL_BUF_STATE = 2,   /* descriptors, walker and problem state, scratch */
     REWL_NBUF = 3
@@ -150,6 +181,14 @@ rewl_status rewl_plan_bind(rewl_plan* plan, void* const* dev_ptrs, void* hip_str
  * or magnetization bins (magnetization split). */
 rewl_status rewl_window_bounds(const rewl_plan* plan, int32_t prob, int32_t w,
                                int32_t* e_lo, int32_t* e_hi);
+
+/* Rectangle [e_lo, e_hi] x [m_lo, m_hi] (energy and magnetization bins) of
+ * window w of problem prob, for any split. */
+rewl_status rewl_window_rect(const rewl_plan* plan, int32_t prob, int32_t w, int32_t* e_lo,
+                             int32_t* e_hi, int32_t* m_lo, int32_t* m_hi);
+
+/* Windows of problem prob (for REWL_SPLIT_BOTH the kept rectangles). */
+rewl_status rewl_plan_windows(const rewl_plan* plan, int32_t prob, int32_t* n_windows);
 
 /* Counts of the plan: problems, walkers in total. */
 rewl_status rewl_plan_counts(const rewl_plan* plan, int32_t* n_problems, int64_t* n_walkers);
@@ -240,6 +279,23 @@ rewl_status rewl_lnz_backward(const double* lng, int32_t N, int32_t e0, int32_t 
                               double* grad_beta, double* grad_h, double* grad_lng,
                               double* mom, int32_t order, void* hip_stream);
 
+/* Second order: the backward of rewl_lnz_backward's (grad_beta, grad_h) with
+ * respect to (grad_out, beta, h), so that specific heat and susceptibility
+ * come out as gradients of gradients (d2 ln Z / d beta2 = Var(U), d2 ln Z /
+ * d h2 = beta^2 Var(M), d2 ln Z / d beta d h = <M> + beta Cov(U, M), U = -E
+ * + h M).  Inputs per grid point (G entries, device): grad_out g (NULL =
+ * all ones) and the upstream gradients a of grad_beta and c of grad_h (each
+ * NULL = zeros).  Outputs (G entries each, required):
+ *   d_grad_out = a <U> + c beta <M>
+ *   d_beta     = g (a Var(U) + c (<M> + beta Cov(U, M)))
+ *   d_h        = g (a (<M> + beta Cov(U, M)) + c beta^2 Var(M)).
+ * Dependence on ln g is not differentiated.  Enqueued on hip_stream. */
+rewl_status rewl_lnz_backward2(const double* lng, int32_t N, int32_t e0, int32_t nE,
+                               int32_t m0, int32_t nM, const double* beta, const double* h,
+                               int64_t G, const double* lnz, const double* grad_out,
+                               const double* up_beta, const double* up_h, double* d_grad_out,
+                               double* d_beta, double* d_h, void* hip_stream);
+
 /* Reweighting on a tensor-product grid beta[0..nB) x h[0..nH): lnz[i*nH + j]
  * = ln Z(beta[i], h[j]), the same quantity as rewl_lnz_forward at those
  * points (equal up to the order of rounding).  The sum is factorised through
@@ -269,6 +325,22 @@ rewl_status rewl_lnz_grid_backward(const double* lng, int32_t N, int32_t e0, int
                                    const double* grad_out, void* workspace, size_t workspace_bytes,
                                    double* grad_beta, double* grad_h, double* grad_lng, double* mom,
                                    void* hip_stream);
+
+/* Second order on a tensor-product grid: the backward of
+ * rewl_lnz_grid_backward's (grad_beta (nB), grad_h (nH)) given their upstream
+ * gradients up_beta (nB) and up_h (nH) (each NULL = zeros) and the first
+ * order's grad_out (nB x nH, NULL = all ones).  Per point (i, j) the terms of
+ * rewl_lnz_backward2 with a = up_beta[i], c = up_h[j]; outputs d_grad_out
+ * (nB x nH), d_beta[i] = sum_j of the point terms, d_h[j] = sum_i of them
+ * (fixed summation order).  `workspace` as for rewl_lnz_grid_forward.
+ * Enqueued on hip_stream. */
+rewl_status rewl_lnz_grid_backward2(const double* lng, int32_t N, int32_t e0, int32_t nE,
+                                    int32_t m0, int32_t nM, const double* beta, int64_t nB,
+                                    const double* h, int64_t nH, const double* lnz,
+                                    const double* grad_out, const double* up_beta,
+                                    const double* up_h, void* workspace, size_t workspace_bytes,
+                                    double* d_grad_out, double* d_beta, double* d_h,
+                                    void* hip_stream);
 
 /* Replace the tuning of a plan (same form); results do not change. */
 rewl_status rewl_set_tuning(rewl_plan* plan, const rewl_tuning* tuning);

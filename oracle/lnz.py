@@ -87,3 +87,27 @@ def grads(lng, beta, h, grad_out=None):
         x = _terms(lng, N, b, hh)
         g_lng += go.flat[i] * np.exp(x - mo["lnz"].flat[i])
     return g_beta, g_h, g_lng
+
+
+def second(lng, beta, h, grad_out=None, up_beta=None, up_h=None):
+    """Backward of the first-order products (g_beta, g_h) = (g <U>, g beta <M>).
+
+    With upstream gradients a (of g_beta) and c (of g_h), per grid point:
+        d grad_out = a <U> + c beta <M>
+        d beta     = g (a Var(U) + c (<M> + beta Cov(U, M)))
+        d h        = g (a (<M> + beta Cov(U, M)) + c beta^2 Var(M))
+    i.e. the Hessian of ln Z in (beta, h) applied to (a, c), times g, and
+    the gradient (a, c) . (d lnZ/d beta, d lnZ/d h)."""
+    mo = moments(lng, beta, h)
+    shape = mo["lnz"].shape
+    b = np.broadcast_to(np.asarray(beta, np.float64), shape)
+    hh = np.broadcast_to(np.asarray(h, np.float64), shape)
+    g = np.ones(shape) if grad_out is None else np.asarray(grad_out, np.float64)
+    a = np.zeros(shape) if up_beta is None else np.asarray(up_beta, np.float64)
+    c = np.zeros(shape) if up_h is None else np.asarray(up_h, np.float64)
+    mU = -mo["E"] + hh * mo["M"]
+    cross = mo["M"] + b * mo["covUM"]
+    d_go = a * mU + c * b * mo["M"]
+    d_beta = g * (a * mo["varU"] + c * cross)
+    d_h = g * (a * cross + c * b * b * mo["varM"])
+    return d_go, d_beta, d_h

@@ -86,6 +86,12 @@ def lib():
         L.or_n_windows.restype = C.c_int
         L.or_realizable.argtypes = [C.c_int] * 3
         L.or_realizable.restype = C.c_int
+        L.or_set_hist.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+        L.or_set_hist.restype = None
+        L.or_draw_matching.argtypes = [C.c_uint64, C.c_int64, C.c_int, C.c_int, C.POINTER(C.c_int)]
+        L.or_draw_matching.restype = None
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_set_threads.restype = C.c_int
         L.or_window_state.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int),
                                       C.POINTER(C.c_int)]
         L.or_window_state.restype = None
@@ -123,6 +129,19 @@ def window(N, n, p, q, i):
 def realizable(L, e, m):
     """Whether bin (e, m) holds a state, by the closed-form support (or_realizable)."""
     return bool(lib().or_realizable(int(L), int(e), int(m)))
+
+
+def set_threads(n):
+    """Host threads for the oracle's walker loops (0 = unchanged); returns the count in effect."""
+    return int(lib().or_set_threads(int(n)))
+
+
+def draw_matching(seed, r, w, W):
+    """The exchange matching of round r for the window pair with lower window w: walker a of
+    the lower window meets walker pi[a] of the upper one."""
+    pi = (C.c_int * W)()
+    lib().or_draw_matching(seed & 0xFFFFFFFFFFFFFFFF, int(r), int(w), int(W), pi)
+    return tuple(pi)
 
 
 def energy(spins, L):
@@ -244,6 +263,11 @@ class OracleREWL:
         return {"lng": lng, "H": H, "spins": sp.reshape(self.L, self.L),
                 "e": e.value, "m": m.value, "t": t.value, "te": te.value,
                 "flag": fl.value, "lo": lo, "hi": hi}
+
+    def set_hist(self, g, H):
+        """Overwrite walker g's visit histogram (window-table shape, uint64)."""
+        a = np.ascontiguousarray(H, np.uint64)
+        lib().or_set_hist(self._h, g, a.ctypes.data)
 
     def set_stage(self, s):
         lib().or_set_stage(self._h, s)

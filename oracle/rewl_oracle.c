@@ -34,6 +34,7 @@
  *        -fopenmp rewl_oracle.c -o liboracle.so -lm
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -484,6 +485,23 @@ static int pair_active(const or_rewl *P, int k, int64_t r) {
     return P->pdir[k] == (int)((r >> 1) & 1) && (P->palong[k] & 1) == (int)(r & 1);
 }
 
+/* The random matching of round r for the pair whose lower window is w: a    */
+/* Fisher-Yates shuffle of (0 .. W-1), position i (from W-1 down to 1)       */
+/* exchanged with position j = floor(word * (i + 1) / 2^32), the word taken  */
+/* from the XPERM stream at (r, w, i).  Walker a of the lower window meets   */
+/* walker pi[a] of the upper one.                                             */
+OR_EXPORT void or_draw_matching(uint64_t seed, int64_t r, int w, int W, int *pi) {
+    for (int a = 0; a < W; ++a) pi[a] = a;
+    for (int i = W - 1; i >= 1; --i) {
+        uint32_t ctr[4] = {(uint32_t)r, (uint32_t)((uint64_t)r >> 32),
+                           (uint32_t)w, ((uint32_t)TAG_XPERM << 24) | (uint32_t)i};
+        uint32_t out[4];
+        or_philox((uint32_t)seed, (uint32_t)(seed >> 32), ctr, out);
+        int j = (int)(((uint64_t)out[0] * (uint64_t)(i + 1)) >> 32);
+        int tmp = pi[i]; pi[i] = pi[j]; pi[j] = tmp;
+    }
+}
+
 OR_EXPORT int64_t or_exchange(or_rewl *P, int64_t r) {
     int W = P->W;
     int64_t n_acc = 0;
@@ -491,15 +509,7 @@ OR_EXPORT int64_t or_exchange(or_rewl *P, int64_t r) {
     for (int k = 0; k < P->n_pairs; ++k) {
         if (!pair_active(P, k, r)) continue;
         int w = P->pa[k], v = P->pb[k];
-        for (int a = 0; a < W; ++a) pi[a] = a;
-        for (int i = W - 1; i >= 1; --i) {
-            uint32_t ctr[4] = {(uint32_t)r, (uint32_t)((uint64_t)r >> 32),
-                               (uint32_t)w, ((uint32_t)TAG_XPERM << 24) | (uint32_t)i};
-            uint32_t out[4];
-            or_philox((uint32_t)P->seed, (uint32_t)(P->seed >> 32), ctr, out);
-            int j = (int)(((uint64_t)out[0] * (uint64_t)(i + 1)) >> 32);
-            int tmp = pi[i]; pi[i] = pi[j]; pi[j] = tmp;
-        }
+        or_draw_matching(P->seed, r, w, W, pi);
         for (int a = 0; a < W; ++a) {
             int A = w * W + a, B = v * W + pi[a];
             int eA = P->e[A], mA = P->m[A], eB = P->e[B], mB = P->m[B];
@@ -778,6 +788,12 @@ OR_EXPORT void or_set_walker(or_rewl *P, int g, const int64_t *lng,
     }
 }
 
+/* Overwrite a walker's visit histogram H of the current stage (tests of the */
+/* flatness rule on hand-made tables). */
+OR_EXPORT void or_set_hist(or_rewl *P, int g, const uint64_t *H) {
+    memcpy(P->H[g], H, sizeof(uint64_t) * (size_t)bins_of(P, win_of(P, g)));
+}
+
 /* Set the stage index s (ln f = 2^-s) of every window and clear the flatness
  * latches; used by statistical tests that run the walk at a fixed, negligible
  * ln f. */
@@ -798,6 +814,13 @@ OR_EXPORT int or_set_split(or_rewl *P, int split) {
     P->split = split;
     rects_from_split(P);
     return 0;
+}
+
+/* Number of host threads the walker loops may use (0 = leave as is);      */
+/* returns the number now in effect.  Results do not depend on it.           */
+OR_EXPORT int or_set_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }
 
 OR_EXPORT int or_set_sync(or_rewl *P, int sync) {

@@ -24,7 +24,9 @@ REWL_OK, REWL_EINVAL, REWL_ENOMEM, REWL_EDEVICE, REWL_ESTATE, REWL_EOVERFLOW, RE
     0, -1, -2, -3, -4, -5, -6
 FORM_BATCHED, FORM_PLAIN = 0, 1
 SYNC_PROBLEM, SYNC_WINDOW = 0, 1
-SPLIT_ENERGY, SPLIT_MAGNETIZATION = 0, 1
+SPLIT_ENERGY, SPLIT_MAGNETIZATION, SPLIT_BOTH = 0, 1, 2
+LAYOUT_DENSE, LAYOUT_BAND = 0, 1
+LAYOUTS = (LAYOUT_DENSE, LAYOUT_BAND)
 NBUF = 3
 
 
@@ -39,13 +41,14 @@ class _Problem(C.Structure):
                 ("overlap_den", C.c_int32), ("walkers_per_window", C.c_int32), ("k_final", C.c_int32),
                 ("flat_num", C.c_int32), ("flat_den", C.c_int32), ("interval", C.c_int64),
                 ("seed", C.c_uint64), ("init", C.c_int32), ("stage_sync", C.c_int32),
-                ("split", C.c_int32), ("reserved", C.c_int32)]
+                ("split", C.c_int32), ("m_windows", C.c_int32), ("m_overlap_num", C.c_int32),
+                ("m_overlap_den", C.c_int32), ("reserved", C.c_int32)]
 
 
 class _Tuning(C.Structure):
     _fields_ = [("form", C.c_int32), ("walkers_per_wg", C.c_int32), ("graph_intervals", C.c_int32),
                 ("grid_waves_per_cu", C.c_int32), ("profile", C.c_int32), ("walkers_per_wave", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("table_layout", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -67,6 +70,8 @@ def lib():
             "rewl_plan_bind": ([P, C.POINTER(P), P], C.c_int),
             "rewl_window_bounds": ([P, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
             "rewl_plan_counts": ([P, C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int),
+            "rewl_window_rect": ([P, C.c_int32, C.c_int32] + [C.POINTER(C.c_int32)] * 4, C.c_int),
+            "rewl_plan_windows": ([P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
             "rewl_init": ([P], C.c_int),
             "rewl_run": ([P, C.c_int64], C.c_int),
             "rewl_sweep": ([P, C.c_int64], C.c_int),
@@ -85,6 +90,10 @@ def lib():
                                        P, C.c_int64, P, C.c_size_t, P, P], C.c_int),
             "rewl_lnz_grid_backward": ([P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, C.c_int64,
                                         P, C.c_int64, P, P, P, C.c_size_t, P, P, P, P, P], C.c_int),
+            "rewl_lnz_backward2": ([P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_int64,
+                                    P, P, P, P, P, P, P, P], C.c_int),
+            "rewl_lnz_grid_backward2": ([P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, C.c_int64,
+                                         P, C.c_int64, P, P, P, P, P, C.c_size_t, P, P, P, P], C.c_int),
             "rewl_sweep_times": ([P, P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
             "rewl_set_profile": ([P, C.c_int32], C.c_int),
             "rewl_merge_workspace_size": ([P, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
@@ -114,8 +123,10 @@ class Problem:
 
     stage_sync: SYNC_PROBLEM (all windows refine ln f together, the paper) or
     SYNC_WINDOW (each window averages its walkers' ln g and refines alone).
-    split: SPLIT_ENERGY (windows over E, the paper's runs) or SPLIT_MAGNETIZATION
-    (windows over M with every energy, the alternative of Sec. 2); one per plan."""
+    split: SPLIT_ENERGY (windows over E, the paper's runs), SPLIT_MAGNETIZATION
+    (windows over M with every energy, the alternative of Sec. 2) or SPLIT_BOTH
+    (the rectangles of n_windows energy windows x m_windows magnetization windows
+    that hold states, the second alternative of Sec. 2); one per plan."""
     L: int
     n_windows: int = 1
     overlap: tuple = (3, 4)
@@ -127,11 +138,14 @@ class Problem:
     init: int = 0
     stage_sync: int = SYNC_PROBLEM
     split: int = SPLIT_ENERGY
+    m_windows: int = 0
+    m_overlap: tuple = (0, 0)
 
     def _c(self):
         return _Problem(self.L, self.n_windows, self.overlap[0], self.overlap[1], self.walkers_per_window,
                         self.k_final, self.flat[0], self.flat[1], self.interval,
-                        self.seed & 0xFFFFFFFFFFFFFFFF, self.init, self.stage_sync, self.split, 0)
+                        self.seed & 0xFFFFFFFFFFFFFFFF, self.init, self.stage_sync, self.split,
+                        self.m_windows, self.m_overlap[0], self.m_overlap[1], 0)
 
     @property
     def N(self):
@@ -146,10 +160,25 @@ class Tuning:
     grid_waves_per_cu: int = 0
     profile: int = 0
     walkers_per_wave: int = 0
+    table_layout: int = LAYOUT_DENSE
 
     def _c(self):
         return _Tuning(self.form, self.walkers_per_wg, self.graph_intervals, self.grid_waves_per_cu,
-                       self.profile, self.walkers_per_wave, (C.c_int32 * 2)(0, 0))
+                       self.profile, self.walkers_per_wave, self.table_layout, 0)
+
+
+def plan_bytes(problems, table_layout=LAYOUT_DENSE):
+    """Device bytes a plan of `problems` needs (all three buffers), without binding it."""
+    arr = (_Problem * len(problems))(*[p._c() for p in problems])
+    h = C.c_void_p()
+    _check(lib().rewl_plan_create(arr, len(problems), C.byref(Tuning(table_layout=table_layout)._c()),
+                                  C.byref(h)))
+    try:
+        sizes = (C.c_size_t * NBUF)()
+        _check(lib().rewl_plan_buffer_sizes(h, sizes))
+        return int(sum(sizes))
+    finally:
+        lib().rewl_plan_destroy(h)
 
 
 class Plan:
@@ -181,12 +210,33 @@ class Plan:
         nw = C.c_int64()
         _check(lib().rewl_plan_counts(h, C.byref(npb), C.byref(nw)))
         self.n_problems, self.n_walkers = npb.value, nw.value
+        self.windows_of = []
+        for i in range(self.n_problems):
+            k = C.c_int32()
+            _check(lib().rewl_plan_windows(h, i, C.byref(k)))
+            self.windows_of.append(k.value)
 
-    def __del__(self):
+    def close(self):
+        """Destroy the plan after its stream has drained, then release the buffers.
+
+        The buffers come from the caching allocator on the current stream but
+        are written on ``self.stream``; rewl_plan_destroy waits for that stream,
+        so no kernel of the plan can still touch a buffer once it is handed
+        back to the allocator."""
         h = getattr(self, "_h", None)
         if h is not None and h.value and _lib is not None:
             _lib.rewl_plan_destroy(h)
-            self._h = None
+        self._h = None
+        st = getattr(self, "stream", None)
+        if st is not None:
+            st.synchronize()
+        self.buffers = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: torch may already be gone
+            pass
 
     # ----- the paper's operations
     def init(self):
@@ -214,7 +264,7 @@ class Plan:
 
     def query_windows(self, prob=0):
         """Per window of problem prob: stage, done, trials per walker."""
-        n = self.problems[prob].n_windows
+        n = self.windows_of[prob]
         st = np.zeros(n, np.int32)
         dn = np.zeros(n, np.int32)
         tr = np.zeros(n, np.int64)
@@ -273,12 +323,19 @@ class Plan:
         _check(lib().rewl_window_bounds(self._h, prob, w, C.byref(lo), C.byref(hi)))
         return lo.value, hi.value
 
+    def window_rect(self, prob, w):
+        """(e_lo, e_hi, m_lo, m_hi) of window w of problem prob."""
+        r = [C.c_int32() for _ in range(4)]
+        _check(lib().rewl_window_rect(self._h, prob, w, *[C.byref(x) for x in r]))
+        return tuple(x.value for x in r)
+
     def walker(self, prob, w, a, tables=True):
-        """Walker a of window w of problem prob: lng / H tables (rows e - lo, cols m; for the
-        magnetization split rows e, cols m - lo), spins, e, m, t."""
+        """Walker a of window w of problem prob: lng / H tables over the window's rectangle
+        (rows e - e_lo, columns m - m_lo), spins, e, m, t."""
         p = self.problems[prob]
         lo, hi = self.window(prob, w)
-        nb = (hi - lo + 1) * (p.N + 1)
+        elo, ehi, mlo, mhi = self.window_rect(prob, w)
+        nb = (ehi - elo + 1) * (mhi - mlo + 1)
         lng = np.zeros(nb, np.int64) if tables else None
         H = np.zeros(nb, np.uint64) if tables else None
         sp = np.zeros(p.N, np.int8)
@@ -287,7 +344,7 @@ class Plan:
                                       lng.ctypes.data if tables else None,
                                       H.ctypes.data if tables else None, nb if tables else 0,
                                       sp.ctypes.data, C.byref(e), C.byref(m), C.byref(t)))
-        shape = (p.N + 1, hi - lo + 1) if p.split else (hi - lo + 1, p.N + 1)
+        shape = (ehi - elo + 1, mhi - mlo + 1)
         return {"lng": None if lng is None else lng.reshape(shape),
                 "H": None if H is None else H.reshape(shape),
                 "spins": sp.reshape(p.L, p.L), "e": e.value, "m": m.value, "t": t.value,
@@ -340,6 +397,20 @@ def _lnz_grads(lng, beta, h, lnz, grad_out, N, e0, m0, want_lng):
     return gb, gh, gl
 
 
+def lnz_second(lng, beta, h, lnz, grad_out, up_beta, up_h, N, e0=0, m0=0):
+    """Backward of (grad_beta, grad_h) = first-order backward of ln Z: (d grad_out, d beta, d h), each (G,)."""
+    import torch
+    d_go, d_b, d_h = (torch.empty_like(beta) for _ in range(3))
+    st = torch.cuda.current_stream(lng.device).cuda_stream
+    _check(lib().rewl_lnz_backward2(_ptr(lng), *_geom(lng, N, e0, m0), _ptr(beta.contiguous()),
+                                    _ptr(h.contiguous()), beta.numel(), _ptr(lnz.contiguous()),
+                                    _ptr(None if grad_out is None else grad_out.contiguous()),
+                                    _ptr(None if up_beta is None else up_beta.contiguous()),
+                                    _ptr(None if up_h is None else up_h.contiguous()),
+                                    _ptr(d_go), _ptr(d_b), _ptr(d_h), C.c_void_p(st)))
+    return d_go, d_b, d_h
+
+
 def _grid_ws(lng, nB, nH):
     import torch
     nb = C.c_size_t()
@@ -379,6 +450,32 @@ def lnz_grid_backward(lng, beta, h, lnz, grad_out, N, e0=0, m0=0, want_grads=Tru
     return gb, gh, gl, mom
 
 
+def lnz_grid_second(lng, beta, h, lnz, grad_out, up_beta, up_h, N, e0=0, m0=0):
+    """Second order on a grid: (d grad_out (nB, nH), d beta (nB), d h (nH)) on the device."""
+    import torch
+    nB, nH = beta.numel(), h.numel()
+    d_go = torch.empty((nB, nH), dtype=torch.float64, device=lng.device)
+    d_b = torch.empty(nB, dtype=torch.float64, device=lng.device)
+    d_h = torch.empty(nH, dtype=torch.float64, device=lng.device)
+    ws, nb = _grid_ws(lng, nB, nH)
+    st = torch.cuda.current_stream(lng.device).cuda_stream
+    _check(lib().rewl_lnz_grid_backward2(_ptr(lng), *_geom(lng, N, e0, m0), _ptr(beta.contiguous()), nB,
+                                         _ptr(h.contiguous()), nH, _ptr(lnz.contiguous()),
+                                         _ptr(None if grad_out is None else grad_out.contiguous()),
+                                         _ptr(None if up_beta is None else up_beta.contiguous()),
+                                         _ptr(None if up_h is None else up_h.contiguous()),
+                                         _ptr(ws), nb, _ptr(d_go), _ptr(d_b), _ptr(d_h), C.c_void_p(st)))
+    return d_go, d_b, d_h
+
+
+def _no_lng_second_order(ctx, name):
+    """Second derivatives through ln g are not provided: refuse instead of dropping them."""
+    import torch
+    if ctx.needs_input_grad[0] and torch.is_grad_enabled():
+        raise RuntimeError(f"{name}: second derivatives with respect to ln g are not implemented "
+                           "(differentiate twice with respect to beta and h only)")
+
+
 def _torch_functions():
     import torch
 
@@ -396,14 +493,7 @@ def _torch_functions():
         def backward(ctx, a, b):
             grad_out, beta, h, lng, lnz = ctx.saved_tensors
             N, e0, m0 = ctx.geo
-            mom = lnz_moments(lng, beta, h, lnz, N, e0, m0)
-            mM, mU, vU, vM, cUM = mom.unbind(1)
-            a = torch.zeros_like(beta) if a is None else a
-            b = torch.zeros_like(beta) if b is None else b
-            cross = mM + beta * cUM
-            d_go = a * mU + b * beta * mM
-            d_beta = grad_out * (a * vU + b * cross)
-            d_h = grad_out * (a * cross + b * beta * beta * vM)
+            d_go, d_beta, d_h = lnz_second(lng, beta.detach(), h.detach(), lnz, grad_out.detach(), a, b, N, e0, m0)
             return d_go, d_beta, d_h, None, None, None, None, None
 
     class LnZ(torch.autograd.Function):
@@ -424,6 +514,7 @@ def _torch_functions():
         def backward(ctx, grad_out):
             lng, beta, h, lnz = ctx.saved_tensors
             N, e0, m0 = ctx.geo
+            _no_lng_second_order(ctx, "LnZ")
             g_lng = None
             if ctx.needs_input_grad[0]:
                 _, _, g_lng = _lnz_grads(lng, beta.detach(), h.detach(), lnz, grad_out.detach(), N, e0, m0, True)
@@ -444,15 +535,8 @@ def _torch_functions():
         def backward(ctx, a, b):
             grad_out, beta, h, lng, lnz = ctx.saved_tensors
             N, e0, m0 = ctx.geo
-            _, _, _, mom = lnz_grid_backward(lng, beta, h, lnz, None, N, e0, m0, want_grads=False, want_mom=True)
-            mM, mU, vU, vM, cUM = mom.unbind(2)
-            a = torch.zeros_like(beta) if a is None else a
-            b = torch.zeros_like(h) if b is None else b
-            bi = beta[:, None]
-            cross = mM + bi * cUM
-            d_go = a[:, None] * mU + b[None, :] * bi * mM
-            d_beta = (grad_out * (a[:, None] * vU + b[None, :] * cross)).sum(1)
-            d_h = (grad_out * (a[:, None] * cross + b[None, :] * bi * bi * vM)).sum(0)
+            d_go, d_beta, d_h = lnz_grid_second(lng, beta.detach(), h.detach(), lnz, grad_out.detach(), a, b, N,
+                                                e0, m0)
             return d_go, d_beta, d_h, None, None, None, None, None
 
     class LnZGrid(torch.autograd.Function):
@@ -472,6 +556,7 @@ def _torch_functions():
         def backward(ctx, grad_out):
             lng, beta, h, lnz = ctx.saved_tensors
             N, e0, m0 = ctx.geo
+            _no_lng_second_order(ctx, "LnZGrid")
             g_lng = None
             if ctx.needs_input_grad[0]:
                 _, _, g_lng, _ = lnz_grid_backward(lng, beta.detach(), h.detach(), lnz, grad_out.detach(), N, e0,

@@ -93,9 +93,16 @@ __global__ void __launch_bounds__(TILE) k_lnz_fwd(Geo geo, const double* __restr
 // U = -E + h M: <M>, <U> in a first pass, then Var(U), Var(M), Cov(U, M) as
 // central sums about those means in a second pass (no cancellation of large
 // raw moments at low temperature or strong field).
+// With upstream gradients a = up_b, c = up_h of (grad_beta, grad_h) it also
+// writes the second-order terms of the backward of the first-order backward
+// (d2 != nullptr): with g = grad_out and cross = <M> + beta Cov(U, M),
+//   d grad_out = a <U> + c beta <M>
+//   d beta     = g (a Var(U) + c cross)
+//   d h        = g (a cross + c beta^2 Var(M)).
 __global__ void __launch_bounds__(TILE) k_lnz_mom(Geo geo, const double* beta, const double* hf, int64_t G,
                                                    const double* lnz, const double* gout, double* mom,
-                                                   double* gbeta, double* gh) {
+                                                   double* gbeta, double* gh, const double* up_b,
+                                                   const double* up_h, double* d_go, double* d_b, double* d_h) {
     __shared__ double sl[TILE], sE[TILE], sM[TILE];
     const int64_t gp = static_cast<int64_t>(blockIdx.x) * TILE + threadIdx.x;
     const bool on = gp < G;
@@ -154,6 +161,13 @@ __global__ void __launch_bounds__(TILE) k_lnz_mom(Geo geo, const double* beta, c
     const double go = gout ? gout[gp] : 1.0;
     if (gbeta) gbeta[gp] = go * mU;
     if (gh) gh[gp] = go * b * mM;
+    if (d_go) {
+        const double a = up_b ? up_b[gp] : 0.0, c = up_h ? up_h[gp] : 0.0;
+        const double cross = mM + b * cUM;
+        d_go[gp] = a * mU + c * (b * mM);
+        d_b[gp] = go * (a * vU + c * cross);
+        d_h[gp] = go * (a * cross + c * (b * b * vM));
+    }
 }
 
 // grad ln g(E,M) = sum_g grad_out_g p_g(E,M): one thread per bin, grid points
@@ -320,11 +334,16 @@ __global__ void __launch_bounds__(TILE) k_grid_rows(const double* A, int N, int 
 // beta_i h_j M - ln Z) and the conditional mean of U = -E + h M in column M,
 // ubar = -u1 + h M: <M>, <U>, then Var(U) = sum p (u2 + (ubar - <U>)^2),
 // Var(M), Cov(U, M) = sum p (ubar - <U>)(M - <M>) about those means.  Also
-// the per-point terms of the gradients: tb = g <U>, th = g beta <M>.
+// the per-point terms of the gradients: tb = g <U>, th = g beta <M>; or, for
+// the second order (d_go != nullptr, upstream a_i = up_b[i], c_j = up_h[j]),
+// d grad_out = a_i <U> + c_j beta_i <M> and the per-point terms of d beta and
+// d h, tb = g (a_i Var(U) + c_j cross), th = g (a_i cross + c_j beta_i^2
+// Var(M)) with cross = <M> + beta_i Cov(U, M), summed over j and i afterwards.
 __global__ void __launch_bounds__(TILE) k_grid_mom(const double* A, const double* u1, const double* u2, int N,
                                                     int m0, int nM, const double* beta, const double* hf,
                                                     int64_t nH, const double* lnz, const double* gout,
-                                                    double* mom, double* tb, double* th) {
+                                                    double* mom, double* tb, double* th, const double* up_b,
+                                                    const double* up_h, double* d_go) {
     __shared__ double sa[TILE], s1[TILE], s2[TILE];
     const int64_t i = blockIdx.x;
     const int64_t j = static_cast<int64_t>(blockIdx.y) * TILE + threadIdx.x;
@@ -377,8 +396,14 @@ __global__ void __launch_bounds__(TILE) k_grid_mom(const double* A, const double
         mom[5 * o + 3] = vM / c0;
         mom[5 * o + 4] = cUM / c0;
     }
-    if (tb) {
-        const double go = gout ? gout[o] : 1.0;
+    const double go = gout ? gout[o] : 1.0;
+    if (d_go) {
+        const double a = up_b ? up_b[i] : 0.0, c = up_h ? up_h[j] : 0.0;
+        const double vUn = vU / c0, vMn = vM / c0, cross = mM + b * (cUM / c0);
+        d_go[o] = a * mU + c * (b * mM);
+        tb[o] = go * (a * vUn + c * cross);
+        th[o] = go * (a * cross + c * (b * b * vMn));
+    } else if (tb) {
         tb[o] = go * mU;
         th[o] = go * b * mM;
     }
@@ -486,7 +511,20 @@ hipError_t launch_lnz_moments(const double* lng, int N, int e0, int nE, int m0, 
                               double* gbeta, double* gh, hipStream_t st) {
     if (G <= 0) return hipSuccess;
     Geo geo{lng, N, e0, nE, m0, nM};
-    hipLaunchKernelGGL(k_lnz_mom, dim3(nblk(G)), dim3(TILE), 0, st, geo, beta, h, G, lnz, gout, mom, gbeta, gh);
+    hipLaunchKernelGGL(k_lnz_mom, dim3(nblk(G)), dim3(TILE), 0, st, geo, beta, h, G, lnz, gout, mom, gbeta, gh,
+                       static_cast<const double*>(nullptr), static_cast<const double*>(nullptr),
+                       static_cast<double*>(nullptr), static_cast<double*>(nullptr), static_cast<double*>(nullptr));
+    return hipGetLastError();
+}
+
+hipError_t launch_lnz_second(const double* lng, int N, int e0, int nE, int m0, int nM, const double* beta,
+                             const double* h, int64_t G, const double* lnz, const double* gout, const double* up_b,
+                             const double* up_h, double* d_go, double* d_b, double* d_h, hipStream_t st) {
+    if (G <= 0) return hipSuccess;
+    Geo geo{lng, N, e0, nE, m0, nM};
+    hipLaunchKernelGGL(k_lnz_mom, dim3(nblk(G)), dim3(TILE), 0, st, geo, beta, h, G, lnz, gout,
+                       static_cast<double*>(nullptr), static_cast<double*>(nullptr), static_cast<double*>(nullptr),
+                       up_b, up_h, d_go, d_b, d_h);
     return hipGetLastError();
 }
 
@@ -521,7 +559,8 @@ hipError_t launch_lnz_grid_backward(const double* lng, int N, int e0, int nE, in
                        geo, beta, nB, A, u1, u2);
     if (mom || tb)
         hipLaunchKernelGGL(k_grid_mom, dim3(static_cast<unsigned>(nB), nblk(nH)), dim3(TILE), 0, st, A, u1, u2, N,
-                           m0, nM, beta, h, nH, lnz, gout, mom, tb, th);
+                           m0, nM, beta, h, nH, lnz, gout, mom, tb, th, static_cast<const double*>(nullptr),
+                           static_cast<const double*>(nullptr), static_cast<double*>(nullptr));
     if (tb) {
         hipLaunchKernelGGL(k_grid_sum_rows, dim3(nblk(nB)), dim3(TILE), 0, st, tb, nB, nH, gbeta);
         hipLaunchKernelGGL(k_grid_sum_cols, dim3(static_cast<unsigned>((nH + 63) / 64)), dim3(TILE), 0, st, th, nB,
@@ -533,6 +572,22 @@ hipError_t launch_lnz_grid_backward(const double* lng, int N, int e0, int nE, in
         const int64_t nb = static_cast<int64_t>(nE) * nM;
         hipLaunchKernelGGL(k_grid_glng, dim3(nblk(nb)), dim3(TILE), 0, st, geo, beta, nB, A, cw, glng);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_lnz_grid_second(const double* lng, int N, int e0, int nE, int m0, int nM, const double* beta,
+                                  int64_t nB, const double* h, int64_t nH, const double* lnz, const double* gout,
+                                  const double* up_b, const double* up_h, double* A, double* u1, double* u2,
+                                  double* tb, double* th, double* d_go, double* d_b, double* d_h, hipStream_t st) {
+    if (nB <= 0 || nH <= 0) return hipSuccess;
+    Geo geo{lng, N, e0, nE, m0, nM};
+    hipLaunchKernelGGL(k_grid_cols, dim3(nblk(nM), static_cast<unsigned>((nB + GB - 1) / GB)), dim3(TILE), 0, st,
+                       geo, beta, nB, A, u1, u2);
+    hipLaunchKernelGGL(k_grid_mom, dim3(static_cast<unsigned>(nB), nblk(nH)), dim3(TILE), 0, st, A, u1, u2, N, m0,
+                       nM, beta, h, nH, lnz, gout, static_cast<double*>(nullptr), tb, th, up_b, up_h, d_go);
+    hipLaunchKernelGGL(k_grid_sum_rows, dim3(nblk(nB)), dim3(TILE), 0, st, tb, nB, nH, d_b);
+    hipLaunchKernelGGL(k_grid_sum_cols, dim3(static_cast<unsigned>((nH + 63) / 64)), dim3(TILE), 0, st, th, nB, nH,
+                       d_h);
     return hipGetLastError();
 }
 

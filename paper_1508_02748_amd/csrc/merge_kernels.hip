@@ -30,7 +30,8 @@ namespace rewl {
 namespace {
 
 __device__ __forceinline__ int64_t lng_at(const DevState& S, const WDesc& d, int er, int m) {
-    return S.lng[d.table_off + tile_index(er, m, d.ntm)];
+    const int64_t i = table_index_or_none(d, d.e0 + er, d.m0 + m);
+    return i < 0 ? 0 : S.lng[d.table_off + i];
 }
 
 __global__ void __launch_bounds__(256) k_merge_window(DevState S, MergeGeo G) {

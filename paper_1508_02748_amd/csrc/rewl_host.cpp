@@ -37,6 +37,93 @@ void window_bounds(int N, int n, int p, int q, int i, int& lo, int& hi) {
     hi = static_cast<int>(std::min<long long>(h, N));
 }
 
+// Realizable energy bins at magnetization bin m of the periodic L x L lattice
+// (N = L^2), in closed form.  With k = min(m, N - m) minority spins:
+//   * at most 2k: each unsatisfied bond has a minority spin at one end, and a
+//     spin has four bonds (reached by minority spins on one sublattice);
+//   * at least half the shortest closed domain wall around k sites on the
+//     torus: a compact cluster has perimeter 2 ceil(2 sqrt k); once k >= L a
+//     straight band around the torus needs only 2L bonds when L divides k and
+//     2L + 2 otherwise.
+void energy_range(int L, int m, int& emin, int& emax) {
+    const int N = L * L;
+    const int k = std::min(m, N - m);
+    emax = 2 * k;
+    if (k == 0) {
+        emin = 0;
+        return;
+    }
+    long long t = 0;  // ceil(2 sqrt k): the least t with t^2 >= 4k
+    while (t * t < 4ll * k) ++t;
+    long long wall = 2 * t;
+    if (k >= L) wall = std::min<long long>(wall, 2ll * L + (k % L ? 2 : 0));
+    emin = static_cast<int>(wall / 2);
+}
+
+// Whether some state has energy bin e and magnetization bin m: inside the
+// range above every bin does, except next to m = N/2, where the bin just
+// above the lowest and the two just below the highest are empty at m = N/2,
+// and the one just below the highest at m = N/2 +- 1 (exhaustive enumeration
+// agrees for L = 4 and 6).
+bool holds_state(int L, int e, int m) {
+    int emin, emax;
+    energy_range(L, m, emin, emax);
+    if (e < emin || e > emax) return false;
+    const int N = L * L;
+    if (m == N / 2) return e != emin + 1 && e != emax - 1 && e != emax - 2;
+    if (m == N / 2 - 1 || m == N / 2 + 1) return e != emax - 1;
+    return true;
+}
+
+bool rect_holds_state(int L, int elo, int ehi, int mlo, int mhi) {
+    for (int m = mlo; m <= mhi; ++m)
+        for (int e = elo; e <= ehi; ++e)
+            if (holds_state(L, e, m)) return true;
+    return false;
+}
+
+// The windows of one problem as rectangles of (e, m) bins, e-major, with the
+// neighbouring pairs that may exchange.
+struct Rect {
+    int elo, ehi, mlo, mhi;
+};
+
+void problem_windows(const rewl_problem& q, std::vector<Rect>& rects, std::vector<PairDesc>& pairs, int prob) {
+    const int N = q.L * q.L;
+    rects.clear();
+    pairs.clear();
+    if (q.split != REWL_SPLIT_BOTH) {
+        for (int w = 0; w < q.n_windows; ++w) {
+            int lo, hi;
+            window_bounds(N, q.n_windows, q.overlap_num, q.overlap_den, w, lo, hi);
+            rects.push_back(q.split == REWL_SPLIT_ENERGY ? Rect{lo, hi, 0, N} : Rect{0, N, lo, hi});
+            if (w > 0) pairs.push_back(PairDesc{prob, w - 1, w, 0, w - 1});
+        }
+        return;
+    }
+    const int ne = q.n_windows, nm = q.m_windows;
+    std::vector<int> keep(static_cast<size_t>(ne) * nm, -1);
+    for (int ie = 0; ie < ne; ++ie)
+        for (int im = 0; im < nm; ++im) {
+            Rect r;
+            window_bounds(N, ne, q.overlap_num, q.overlap_den, ie, r.elo, r.ehi);
+            window_bounds(N, nm, q.m_overlap_num, q.m_overlap_den, im, r.mlo, r.mhi);
+            if (rect_holds_state(q.L, r.elo, r.ehi, r.mlo, r.mhi)) {
+                keep[static_cast<size_t>(ie) * nm + im] = static_cast<int>(rects.size());
+                rects.push_back(r);
+            }
+        }
+    for (int ie = 0; ie < ne; ++ie)
+        for (int im = 0; im < nm; ++im) {
+            const int w = keep[static_cast<size_t>(ie) * nm + im];
+            if (w < 0) continue;
+            if (ie + 1 < ne && keep[static_cast<size_t>(ie + 1) * nm + im] >= 0)
+                pairs.push_back(PairDesc{prob, w, keep[static_cast<size_t>(ie + 1) * nm + im], 0, ie});
+            if (im + 1 < nm && keep[static_cast<size_t>(ie) * nm + im + 1] >= 0)
+                pairs.push_back(PairDesc{prob, w, keep[static_cast<size_t>(ie) * nm + im + 1], 1, im});
+        }
+}
+
 }  // namespace
 
 struct rewl_plan {
@@ -45,7 +132,7 @@ struct rewl_plan {
     std::vector<PDesc> pd;
     std::vector<WDesc> wd;
     std::vector<PairDesc> pairs;
-    std::vector<std::vector<int>> lo, hi;  // per problem, per window
+    std::vector<std::vector<Rect>> rect;   // per problem, per window
     int64_t n_walk = 0;
     uint64_t n_bins = 0;
     uint64_t n_words = 0;
@@ -57,7 +144,8 @@ struct rewl_plan {
            off_nseen = 0, off_flag = 0, off_scan = 0, off_stage = 0, off_wdone = 0, off_tstage = 0, off_adv = 0,
            off_lngb = 0, off_tseen = 0, off_done = 0, off_rnd = 0, off_xr = 0, off_xon = 0, off_cnt = 0;
     int32_t n_win = 0;  // windows over all problems
-    int split = 0;      // the split of every problem of the plan (energy 0, magnetization 1)
+    int split = 0;      // the split of every problem of the plan (energy 0, magnetization 1, both 2)
+    int layout = LAYOUT_DENSE;
     // binding
     bool bound = false;
     bool broken = false;
@@ -108,14 +196,26 @@ rewl_status validate(const rewl_problem& q, int idx) {
     if (q.init != 0 && q.init != 1) return bad("init must be 0 or 1");
     if (q.stage_sync != REWL_SYNC_PROBLEM && q.stage_sync != REWL_SYNC_WINDOW)
         return bad("stage_sync must be REWL_SYNC_PROBLEM or REWL_SYNC_WINDOW");
-    if (q.split != REWL_SPLIT_ENERGY && q.split != REWL_SPLIT_MAGNETIZATION)
-        return bad("split must be REWL_SPLIT_ENERGY or REWL_SPLIT_MAGNETIZATION");
+    if (q.split != REWL_SPLIT_ENERGY && q.split != REWL_SPLIT_MAGNETIZATION && q.split != REWL_SPLIT_BOTH)
+        return bad("split must be REWL_SPLIT_ENERGY, REWL_SPLIT_MAGNETIZATION or REWL_SPLIT_BOTH");
     if (q.reserved != 0) return bad("reserved must be 0");
+    if (q.split == REWL_SPLIT_BOTH) {
+        if (q.m_windows < 1 || q.m_overlap_den < 1 || q.m_overlap_num < 0 || q.m_overlap_num >= q.m_overlap_den)
+            return bad("windows in both coordinates need m_windows >= 1 and an overlap num/den < 1");
+        if (static_cast<long long>(q.n_windows) * q.m_windows > 4096) return bad("at most 4096 rectangles");
+    } else if (q.m_windows != 0 || q.m_overlap_num != 0 || q.m_overlap_den != 0) {
+        return bad("m_windows and m_overlap must be 0 unless split is REWL_SPLIT_BOTH");
+    }
     const int N = q.L * q.L;
     for (int i = 0; i < q.n_windows; ++i) {
         int lo, hi;
         window_bounds(N, q.n_windows, q.overlap_num, q.overlap_den, i, lo, hi);
-        if (lo > hi) return bad("too many windows for the energy range");
+        if (lo > hi) return bad("too many windows for the bin range");
+    }
+    for (int i = 0; i < (q.split == REWL_SPLIT_BOTH ? q.m_windows : 0); ++i) {
+        int lo, hi;
+        window_bounds(N, q.m_windows, q.m_overlap_num, q.m_overlap_den, i, lo, hi);
+        if (lo > hi) return bad("too many magnetization windows");
     }
     return REWL_OK;
 }
@@ -129,8 +229,9 @@ rewl_status validate_tuning(const rewl_tuning& tn) {
     if (tn.profile != 0 && tn.profile != 1) return fail(REWL_EINVAL, "profile must be 0 or 1");
     if (tn.walkers_per_wave < 0 || tn.walkers_per_wave > 64) return fail(REWL_EINVAL, "walkers_per_wave 0..64");
     if (tn.profile && tn.form != REWL_FORM_BATCHED) return fail(REWL_EINVAL, "profiling times the batched form");
-    for (int r : tn.reserved)
-        if (r != 0) return fail(REWL_EINVAL, "tuning.reserved must be 0");
+    if (tn.table_layout != REWL_LAYOUT_DENSE && tn.table_layout != REWL_LAYOUT_BAND)
+        return fail(REWL_EINVAL, "table_layout must be REWL_LAYOUT_DENSE or REWL_LAYOUT_BAND");
+    if (tn.reserved != 0) return fail(REWL_EINVAL, "tuning.reserved must be 0");
     return REWL_OK;
 }
 
@@ -195,7 +296,7 @@ int max_grid_of(const rewl_plan* P) {
 rewl_status enqueue_sweep(rewl_plan* P, int64_t n, int ev_slot = -1) {
     if (ev_slot >= 0) HIPCHK(P, hipEventRecord(P->ev[2 * ev_slot], P->stream), "event record");
     HIPCHK(P, launch_sweep(P->S, 0, P->n_walk, n, P->l_max, wg_of(P), max_grid_of(P), P->tune.walkers_per_wave,
-                           P->split, P->stream), "sweep launch");
+                           P->split, P->layout, P->stream), "sweep launch");
     if (ev_slot >= 0) HIPCHK(P, hipEventRecord(P->ev[2 * ev_slot + 1], P->stream), "event record");
     return REWL_OK;
 }
@@ -247,7 +348,8 @@ rewl_status run_interval_plain(rewl_plan* P) {
         const PDesc& q = P->pd[p];
         for (int w = 0; w < q.nwin; ++w) {
             HIPCHK(P, launch_sweep(P->S, q.walker_off + static_cast<int64_t>(w) * q.W, q.W, P->interval,
-                                   q.L, wg, 0, P->tune.walkers_per_wave, P->split, P->stream), "plain sweep launch");
+                                   q.L, wg, 0, P->tune.walkers_per_wave, P->split, P->layout, P->stream),
+                   "plain sweep launch");
         }
     }
     HIPCHK(P, launch_flat(P->S, P->stream), "flatness launch");
@@ -407,6 +509,9 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
         if (problems[i].split != problems[0].split)
             return fail(REWL_EINVAL, "all problems of a plan must share the split");
 
+    if (tn.table_layout == REWL_LAYOUT_BAND && problems[0].split == REWL_SPLIT_BOTH)
+        return fail(REWL_EINVAL, "the band layout applies to one-coordinate splits");
+
     rewl_plan* P = new (std::nothrow) rewl_plan();
     if (!P) return fail(REWL_ENOMEM, "plan allocation");
     P->probs.assign(problems, problems + n_problems);
@@ -414,15 +519,23 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
     P->profile = tn.profile != 0;
     P->interval = X;
     P->split = problems[0].split;
+    P->layout = tn.table_layout;
     int64_t walker = 0;
     uint64_t bins = 0, words = 0;
+    std::vector<Rect> rects;
+    std::vector<PairDesc> pairs;
     for (int p = 0; p < n_problems; ++p) {
         const rewl_problem& q = problems[p];
+        problem_windows(q, rects, pairs, p);
+        if (rects.empty()) {
+            delete P;
+            return fail(REWL_EINVAL, "problem " + std::to_string(p) + ": no window holds a state");
+        }
         PDesc d{};
         d.L = q.L;
         d.N = q.L * q.L;
         d.K = q.k_final;
-        d.nwin = q.n_windows;
+        d.nwin = static_cast<int32_t>(rects.size());
         d.W = q.walkers_per_window;
         d.flat_num = q.flat_num;
         d.flat_den = q.flat_den;
@@ -436,37 +549,53 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
         d.split = static_cast<int16_t>(q.split);
         P->pd.push_back(d);
         P->l_max = std::max(P->l_max, q.L);
-        std::vector<int> los, his;
-        for (int w = 0; w < q.n_windows; ++w) {
-            int lo, hi;
-            window_bounds(d.N, q.n_windows, q.overlap_num, q.overlap_den, w, lo, hi);
-            los.push_back(lo);
-            his.push_back(hi);
+        for (int w = 0; w < d.nwin; ++w) {
+            const Rect& R = rects[w];
+            // stored rows and tile columns of the window's tables
+            int rows = R.ehi - R.elo + 1;
+            uint32_t ntm = static_cast<uint32_t>((R.mhi - R.mlo + 1 + TILE_M - 1) / TILE_M);
+            const bool band = P->layout == REWL_LAYOUT_BAND && q.split == REWL_SPLIT_ENERGY;
+            if (band) {
+                // widest tile row of the band (the lowest one, since the band narrows with e)
+                uint32_t widest = 0;
+                for (int tr = 0; 4 * tr < rows; ++tr) {
+                    const int e = R.elo + 4 * tr;
+                    const int c0 = band_c0(R.elo, tr), c1 = (d.N - (e + 1) / 2) / TILE_M;
+                    widest = std::max<uint32_t>(widest, static_cast<uint32_t>(c1 - c0 + 1));
+                }
+                ntm = widest;
+            } else if (P->layout == REWL_LAYOUT_BAND && q.split == REWL_SPLIT_MAGNETIZATION) {
+                int kmax = 0;
+                for (int m = R.mlo; m <= R.mhi; ++m) kmax = std::max(kmax, std::min(m, d.N - m));
+                rows = std::min(d.N, 2 * kmax) + 1;
+            }
             for (int a = 0; a < q.walkers_per_window; ++a) {
                 WDesc wd{};
                 wd.table_off = bins;
                 wd.spin_off = static_cast<uint32_t>(words);
                 wd.prob = p;
-                wd.lo = lo;
-                wd.hi = hi;
+                wd.lo = q.split == REWL_SPLIT_MAGNETIZATION ? R.mlo : R.elo;
+                wd.hi = q.split == REWL_SPLIT_MAGNETIZATION ? R.mhi : R.ehi;
+                wd.mlo = R.mlo;
+                wd.mhi = R.mhi;
+                wd.e0 = R.elo;
+                wd.m0 = R.mlo;
                 wd.win = w;
                 wd.gid = w * q.walkers_per_window + a;
-                // rows e - lo, all m (energy windows) or all e, columns m - lo (magnetization)
-                const int rows = q.split ? d.N + 1 : hi - lo + 1;
-                const int cols = q.split ? hi - lo + 1 : d.N + 1;
-                wd.ntm = static_cast<uint32_t>((cols + TILE_M - 1) / TILE_M);
-                wd.nbins = static_cast<uint32_t>((rows + TILE_E - 1) / TILE_E) * wd.ntm * TILE_BINS;
+                wd.ntm = ntm;
+                wd.nrows = static_cast<uint32_t>(rows);
+                wd.nbins = static_cast<uint32_t>((rows + TILE_E - 1) / TILE_E) * ntm * TILE_BINS;
+                wd.band = band ? 1 : 0;
                 wd.gwin = P->n_win + w;
                 P->wd.push_back(wd);
                 bins += wd.nbins;
                 words += static_cast<uint64_t>(q.L) * d.row_words;
                 ++walker;
             }
-            if (w + 1 < q.n_windows) P->pairs.push_back(PairDesc{p, w});
         }
-        P->lo.push_back(los);
-        P->hi.push_back(his);
-        P->n_win += q.n_windows;
+        P->pairs.insert(P->pairs.end(), pairs.begin(), pairs.end());
+        P->rect.push_back(rects);
+        P->n_win += d.nwin;
         if (walker >= (1ll << 31) || words >= (1ull << 32)) {
             delete P;
             return fail(REWL_EINVAL, "too many walkers for one plan");
@@ -514,6 +643,9 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
 
 void rewl_plan_destroy(rewl_plan* P) {
     if (!P) return;
+    // work enqueued on the plan's stream may still read or write the caller's
+    // buffers: let it finish before the caller can release them
+    if (P->bound) (void)hipStreamSynchronize(P->stream);
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
     for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     delete P;
@@ -536,8 +668,30 @@ rewl_status rewl_window_bounds(const rewl_plan* P, int32_t prob, int32_t w, int3
     if (!P || !e_lo || !e_hi) return fail(REWL_EINVAL, "null argument");
     if (prob < 0 || prob >= static_cast<int32_t>(P->pd.size())) return fail(REWL_EINVAL, "problem out of range");
     if (w < 0 || w >= P->pd[prob].nwin) return fail(REWL_EINVAL, "window out of range");
-    *e_lo = P->lo[prob][w];
-    *e_hi = P->hi[prob][w];
+    const Rect& R = P->rect[prob][w];
+    const bool m_split = P->split == REWL_SPLIT_MAGNETIZATION;
+    *e_lo = m_split ? R.mlo : R.elo;
+    *e_hi = m_split ? R.mhi : R.ehi;
+    return REWL_OK;
+}
+
+rewl_status rewl_window_rect(const rewl_plan* P, int32_t prob, int32_t w, int32_t* e_lo, int32_t* e_hi,
+                             int32_t* m_lo, int32_t* m_hi) {
+    if (!P || !e_lo || !e_hi || !m_lo || !m_hi) return fail(REWL_EINVAL, "null argument");
+    if (prob < 0 || prob >= static_cast<int32_t>(P->pd.size())) return fail(REWL_EINVAL, "problem out of range");
+    if (w < 0 || w >= P->pd[prob].nwin) return fail(REWL_EINVAL, "window out of range");
+    const Rect& R = P->rect[prob][w];
+    *e_lo = R.elo;
+    *e_hi = R.ehi;
+    *m_lo = R.mlo;
+    *m_hi = R.mhi;
+    return REWL_OK;
+}
+
+rewl_status rewl_plan_windows(const rewl_plan* P, int32_t prob, int32_t* n_windows) {
+    if (!P || !n_windows) return fail(REWL_EINVAL, "null argument");
+    if (prob < 0 || prob >= static_cast<int32_t>(P->pd.size())) return fail(REWL_EINVAL, "problem out of range");
+    *n_windows = P->pd[prob].nwin;
     return REWL_OK;
 }
 
@@ -615,7 +769,8 @@ rewl_status rewl_sweep(rewl_plan* P, int64_t n) {
         for (const PDesc& q : P->pd)
             for (int w = 0; w < q.nwin; ++w)
                 HIPCHK(P, launch_sweep(P->S, q.walker_off + static_cast<int64_t>(w) * q.W, q.W, n, q.L, wg, 0,
-                                       P->tune.walkers_per_wave, P->split, P->stream), "plain sweep launch");
+                                       P->tune.walkers_per_wave, P->split, P->layout, P->stream),
+                       "plain sweep launch");
         return REWL_OK;
     }
     return enqueue_sweep(P, n);
@@ -689,6 +844,7 @@ rewl_status rewl_query(rewl_plan* P, int32_t* stage_out, int32_t* done_out, int6
         if (trials_out) trials_out[p] = t[P->pd[p].walker_off];
     }
     if (cnt[1] & ERR_OVERFLOW) return fail(REWL_EOVERFLOW, "ln g would exceed 2^62 units");
+    if (cnt[1] & ERR_LAYOUT) return fail(REWL_ESTATE, "an exchanged state lies outside a stored table band");
     return REWL_OK;
 }
 
@@ -722,8 +878,9 @@ rewl_status rewl_read_walker(rewl_plan* P, int32_t prob, int32_t w, int32_t a, i
     if (w < 0 || w >= q.nwin || a < 0 || a >= q.W) return fail(REWL_EINVAL, "walker out of range");
     const int64_t g = q.walker_off + static_cast<int64_t>(w) * q.W + a;
     const WDesc& d = P->wd[g];
-    const int nE = q.split ? q.N + 1 : d.hi - d.lo + 1;  // rows of the dense output
-    const int nM = q.split ? d.hi - d.lo + 1 : q.N + 1;  // columns
+    const Rect& R = P->rect[prob][w];
+    const int nE = R.ehi - R.elo + 1;  // rows of the dense output
+    const int nM = R.mhi - R.mlo + 1;  // columns
     const size_t nb = static_cast<size_t>(nE) * nM;
     if ((lng || H) && cap_bins < nb) return fail(REWL_EINVAL, "cap_bins too small");
     std::vector<int64_t> tl, ts;
@@ -752,10 +909,10 @@ rewl_status rewl_read_walker(rewl_plan* P, int32_t prob, int32_t w, int32_t a, i
     if (lng || H)
         for (int er = 0; er < nE; ++er)
             for (int mm = 0; mm < nM; ++mm) {
-                const uint32_t ti = tile_index(er, mm, d.ntm);
+                const int64_t ti = table_index_or_none(d, R.elo + er, R.mlo + mm);
                 const size_t oi = static_cast<size_t>(er) * nM + mm;
-                if (lng) lng[oi] = tl[ti];
-                if (H) H[oi] = static_cast<uint64_t>(tl[ti] - ts[ti]) >> sh;
+                if (lng) lng[oi] = ti < 0 ? 0 : tl[ti];
+                if (H) H[oi] = ti < 0 ? 0 : static_cast<uint64_t>(tl[ti] - ts[ti]) >> sh;
             }
     if (spins)
         for (int r = 0; r < q.L; ++r)
@@ -800,6 +957,19 @@ rewl_status rewl_lnz_backward(const double* lng, int32_t N, int32_t e0, int32_t 
         e = launch_lnz_moments(lng, N, e0, nE, m0, nM, beta, h, G, lnz, nullptr, mom, nullptr, nullptr, st);
     }
     if (e != hipSuccess) return fail(REWL_EDEVICE, std::string("lnz backward: ") + hipGetErrorString(e));
+    return REWL_OK;
+}
+
+rewl_status rewl_lnz_backward2(const double* lng, int32_t N, int32_t e0, int32_t nE, int32_t m0, int32_t nM,
+                               const double* beta, const double* h, int64_t G, const double* lnz,
+                               const double* grad_out, const double* up_beta, const double* up_h, double* d_grad_out,
+                               double* d_beta, double* d_h, void* hip_stream) {
+    if (!lng || !beta || !h || !lnz || !d_grad_out || !d_beta || !d_h) return fail(REWL_EINVAL, "null pointer");
+    if (N < 1 || nE < 1 || nM < 1 || e0 < 0 || m0 < 0 || e0 + nE > N + 1 || m0 + nM > N + 1 || G < 0)
+        return fail(REWL_EINVAL, "bad reweighting geometry");
+    hipError_t e = launch_lnz_second(lng, N, e0, nE, m0, nM, beta, h, G, lnz, grad_out, up_beta, up_h, d_grad_out,
+                                     d_beta, d_h, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(REWL_EDEVICE, std::string("lnz second-order backward: ") + hipGetErrorString(e));
     return REWL_OK;
 }
 
@@ -858,6 +1028,26 @@ rewl_status rewl_lnz_grid_backward(const double* lng, int32_t N, int32_t e0, int
     return REWL_OK;
 }
 
+rewl_status rewl_lnz_grid_backward2(const double* lng, int32_t N, int32_t e0, int32_t nE, int32_t m0, int32_t nM,
+                                    const double* beta, int64_t nB, const double* h, int64_t nH, const double* lnz,
+                                    const double* grad_out, const double* up_beta, const double* up_h,
+                                    void* workspace, size_t workspace_bytes, double* d_grad_out, double* d_beta,
+                                    double* d_h, void* hip_stream) {
+    rewl_status s = grid_check(lng, N, e0, nE, m0, nM, beta, nB, h, nH);
+    if (s != REWL_OK) return s;
+    if (!lnz || !d_grad_out || !d_beta || !d_h || (!workspace && nB * nH > 0)) return fail(REWL_EINVAL, "null pointer");
+    if (workspace_bytes < grid_ws_bytes(nM, nB, nH)) return fail(REWL_EINVAL, "workspace too small");
+    const size_t cm = static_cast<size_t>(nB) * nM, ch = static_cast<size_t>(nB) * nH;
+    double* w = static_cast<double*>(workspace);
+    double *A = w, *u1 = w + cm, *u2 = w + 2 * cm, *tb = w + 4 * cm, *th = tb + ch;
+    hipError_t e = launch_lnz_grid_second(lng, N, e0, nE, m0, nM, beta, nB, h, nH, lnz, grad_out, up_beta, up_h, A,
+                                          u1, u2, tb, th, d_grad_out, d_beta, d_h,
+                                          static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess)
+        return fail(REWL_EDEVICE, std::string("lnz grid second-order backward: ") + hipGetErrorString(e));
+    return REWL_OK;
+}
+
 }  // extern "C"
 
 extern "C" rewl_status rewl_set_profile(rewl_plan* P, int32_t on) {
@@ -877,6 +1067,40 @@ extern "C" rewl_status rewl_sweep_times(rewl_plan* P, float* ms, int32_t cap, in
     for (int i = 0; i < P->ev_used && i < cap; ++i)
         HIPCHK(P, hipEventElapsedTime(&ms[i], P->ev[2 * i], P->ev[2 * i + 1]), "event time");
     *count = P->ev_used;
+    return REWL_OK;
+}
+
+// Self-check of the sweep's acceptance filter (not declared in the public
+// header): runs k_accept_check synchronously on the current device and
+// returns the disagreement, exact-path and acceptance counts, plus the first
+// n_samp pairs and decisions (host arrays, nullable when n_samp = 0).
+extern "C" rewl_status rewl_selfcheck_accept(int32_t K, uint64_t seed, int64_t n, double rel, int64_t* counts_out,
+                                             int64_t* samp_delta, uint32_t* samp_u, int32_t* samp_dec,
+                                             int32_t n_samp) {
+    if (K < 6 || K > 40 || n < 0 || n_samp < 0 || n_samp > n || !counts_out || !(rel >= 0.0))
+        return fail(REWL_EINVAL, "bad self-check arguments");
+    if (n_samp > 0 && (!samp_delta || !samp_u || !samp_dec)) return fail(REWL_EINVAL, "null sample arrays");
+    void* d = nullptr;
+    const size_t ns = static_cast<size_t>(n_samp);
+    const size_t bytes = 32 + ns * (8 + 4 + 4);
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e != hipSuccess) return fail(REWL_EDEVICE, std::string("self-check alloc: ") + hipGetErrorString(e));
+    char* base = static_cast<char*>(d);
+    auto* cnt = reinterpret_cast<unsigned long long*>(base);
+    auto* sd = reinterpret_cast<int64_t*>(base + 32);
+    auto* su = reinterpret_cast<uint32_t*>(base + 32 + ns * 8);
+    auto* sdec = reinterpret_cast<int32_t*>(base + 32 + ns * 12);
+    unsigned long long h[4] = {0, 0, 0, 0};
+    e = hipMemcpy(cnt, h, 32, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_accept_check(K, seed, n, rel, cnt, sd, su, sdec, n_samp, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(h, cnt, 32, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && ns) e = hipMemcpy(samp_delta, sd, ns * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && ns) e = hipMemcpy(samp_u, su, ns * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && ns) e = hipMemcpy(samp_dec, sdec, ns * 4, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(REWL_EDEVICE, std::string("self-check: ") + hipGetErrorString(e));
+    for (int i = 0; i < 3; ++i) counts_out[i] = static_cast<int64_t>(h[i]);
     return REWL_OK;
 }
 
@@ -908,7 +1132,7 @@ rewl_status merge_layout(const rewl_plan* P, int32_t prob, char* base, MergeLayo
     o += 1;
     int max_nE = 0;
     for (int w = 0; w < q.nwin; ++w) {
-        const int nE = P->hi[prob][w] - P->lo[prob][w] + 1;
+        const int nE = P->rect[prob][w].ehi - P->rect[prob][w].elo + 1;
         max_nE = std::max(max_nE, nE);
         G.off_avg[w] = o;
         o += 2 * static_cast<int64_t>(nE) * nM;  // averages, then their standard errors

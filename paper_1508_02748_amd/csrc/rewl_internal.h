@@ -6,24 +6,40 @@
 
 namespace rewl {
 
-// Window tables.  Each walker owns two int64 tables over its window: rows
-// e in [lo, hi] and all m in [0, N] when the windows split the energy, or all
-// rows e in [0, N] and columns m in [lo, hi] when they split the
-// magnetization: ln g in units of 2^-K (> 0 marks a bin
-// the walker has visited; ln g only grows), and a snapshot of ln g taken when
-// the current stage began.  Every visit in stage s adds 2^(K-s), so the visit
-// count of the stage is H = (ln g - snapshot) >> (K - s): a trial touches only
-// ln g, and resetting H at a stage change is one copy of the table.
+// Window tables.  Each walker owns two int64 tables over its window's
+// rectangle of (e, m) bins: rows e in [lo, hi] and all m in [0, N] when the
+// windows split the energy, all rows e and columns m in [lo, hi] when they split
+// the magnetization, both ranges for windows in both coordinates.  The table
+// row is e - e0, the column m - m0 (e0, m0 the rectangle's corner).  They hold
+// ln g in units of 2^-K (> 0 marks a bin the walker has visited; ln g only
+// grows), and a snapshot of ln g taken when the current stage began.  Every
+// visit in stage s adds 2^(K-s), so the visit count of the stage is H = (ln g -
+// snapshot) >> (K - s): a trial touches only ln g, and resetting H at a stage
+// change is one copy of the table.
 //
 // Both tables are stored in tiles of 4 energy rows x 4 magnetization columns
 // (16 bins = 128 bytes, one cache line), tiles row-major: a walker's trial
 // bins (e-2..e+2, m-1 / m+1) fall into about two lines instead of five.
+//
+// Band layout (energy windows): a state in energy bin e has at least e/2
+// minority spins (each unsatisfied bond touches a minority spin, which has four
+// bonds), so its magnetization bin lies in [ceil(e/2), N - ceil(e/2)].  Tile row
+// tr (energies e0 + 4 tr .. e0 + 4 tr + 3) keeps only the tile columns from
+// band_c0 = ceil((e0 + 4 tr)/2) / 4 on, ntm of them, ntm being the widest row
+// of the window.  With windows in magnetization the band layout keeps the
+// energy rows 0 .. 2 k_max only (k_max the largest minority count of the
+// window's m), which needs no change of addressing.
 constexpr int TILE_E = 4, TILE_M = 4, TILE_BINS = TILE_E * TILE_M;
+enum : int32_t { LAYOUT_DENSE = 0, LAYOUT_BAND = 1 };
 
 __host__ __device__ inline uint32_t tile_index(int er, int m, uint32_t ntm) {
     return ((static_cast<uint32_t>(er >> 2) * ntm + static_cast<uint32_t>(m >> 2)) << 4) |
            (static_cast<uint32_t>(er & 3) << 2) | static_cast<uint32_t>(m & 3);
 }
+
+// First stored tile column of tile row tr of a band-layout energy window whose
+// table starts at energy bin e0.
+__host__ __device__ inline int band_c0(int e0, int tr) { return ((e0 + 4 * tr + 1) >> 1) >> 2; }
 
 // Static description of one walker.
 struct WDesc {
@@ -31,15 +47,42 @@ struct WDesc {
                          // offset of the snapshot table)
     uint32_t spin_off;   // first word of its L x row_words packed spins
     int32_t prob;        // problem index
-    int32_t lo, hi;      // window in the split coordinate (e, or m for the magnetization split);
-                         // the table's row is e - lo, column m (energy split), or row e,
-                         // column m - lo (magnetization split)
+    int32_t lo, hi;      // window in the split coordinate (e, or m for the magnetization
+                         // split); the energy range for windows in both coordinates
+    int32_t mlo, mhi;    // magnetization range of the window
+    int32_t e0, m0;      // table origin: row e - e0, column m - m0
     int32_t win;         // window index within the problem
     int32_t gid;         // walker id within the problem: win * W + a
-    uint32_t ntm;        // tiles per table row = ceil(columns / 4)
-    uint32_t nbins;      // bins of its tiled table = ceil(rows / 4) * ntm * 16
+    uint32_t ntm;        // tiles per stored table row
+    uint32_t nbins;      // bins of its tiled table = ceil(nrows / 4) * ntm * 16
+    uint32_t nrows;      // energy rows stored (e - e0 < nrows)
+    int32_t band;        // 1: band addressing of energy windows (band_c0)
     int32_t gwin;        // window index over all problems of the plan
+    int32_t pad_;
 };
+
+// Index of bin (e, m) in a walker's table, for a bin the table stores (any
+// state of the window): BAND = 1 for the band addressing of energy windows.
+template <int BAND>
+__host__ __device__ inline uint32_t table_index(const WDesc& d, int e, int m) {
+    const int er = e - d.e0, mc = m - d.m0;
+    if (BAND) {
+        const int tr = er >> 2;
+        return ((static_cast<uint32_t>(tr) * d.ntm + static_cast<uint32_t>((mc >> 2) - band_c0(d.e0, tr))) << 4) |
+               (static_cast<uint32_t>(er & 3) << 2) | static_cast<uint32_t>(mc & 3);
+    }
+    return tile_index(er, mc, d.ntm);
+}
+
+// Index of any bin (e, m) of the walker's rectangle, or -1 when the table does
+// not store it (no state can be there, so its ln g is 0).
+__host__ __device__ inline int64_t table_index_or_none(const WDesc& d, int e, int m) {
+    const int er = e - d.e0, mc = m - d.m0;
+    if (er < 0 || mc < 0 || er >= static_cast<int>(d.nrows)) return -1;
+    const int tc = (mc >> 2) - (d.band ? band_c0(d.e0, er >> 2) : 0);
+    if (tc < 0 || tc >= static_cast<int>(d.ntm)) return -1;
+    return d.band ? static_cast<int64_t>(table_index<1>(d, e, m)) : static_cast<int64_t>(table_index<0>(d, e, m));
+}
 
 // Static description of one problem.
 struct PDesc {
@@ -50,12 +93,14 @@ struct PDesc {
     int32_t init;
     int32_t win_off;     // first global window index
     int16_t sync;        // 0: all windows change stage together; 1: each window alone
-    int16_t split;       // 0: energy windows; 1: magnetization windows
+    int16_t split;       // 0: energy windows; 1: magnetization windows; 2: both
 };
 
-// A window pair (w, w+1) of one problem that may exchange configurations.
+// A pair of neighbouring windows (wa below wb along direction dir) of one
+// problem that may exchange configurations.  along = index of wa along dir (the
+// window index for one-coordinate splits, its grid row or column otherwise).
 struct PairDesc {
-    int32_t prob, w;
+    int32_t prob, wa, wb, dir, along;
 };
 
 // Device pointers into the three caller buffers.
@@ -94,7 +139,7 @@ struct DevState {
     int32_t n_win;      // windows over all problems
 };
 
-enum : int32_t { ERR_OVERFLOW = 1 };
+enum : int32_t { ERR_OVERFLOW = 1, ERR_LAYOUT = 2 };
 
 // Workspace of the merge of one problem (offsets in doubles from ws).
 constexpr int MERGE_MAX_WINDOWS = 256;
@@ -117,13 +162,15 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_init(const DevState& S, hipStream_t st);
 hipError_t launch_entry(const DevState& S, int64_t cap, hipStream_t st);
 hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int64_t n_trials,
-                        int l_max, int wg, int max_grid, int wpw, int split, hipStream_t st);
+                        int l_max, int wg, int max_grid, int wpw, int split, int layout, hipStream_t st);
 hipError_t sweep_setup();
 hipError_t launch_flat(const DevState& S, hipStream_t st);
 hipError_t launch_stage(const DevState& S, hipStream_t st);
 hipError_t launch_average(const DevState& S, hipStream_t st);
 hipError_t launch_snapshot(const DevState& S, hipStream_t st);
 hipError_t launch_exchange(const DevState& S, hipStream_t st);
+hipError_t launch_accept_check(int K, uint64_t seed, int64_t n, double rel, unsigned long long* counts, int64_t* sd,
+                               uint32_t* su, int32_t* sdec, int n_samp, hipStream_t st);
 
 hipError_t launch_merge(const DevState& S, const MergeGeo& G, int N, int nwin, int max_nE, int norm,
                         double* lng_out, double* lnge_out, int32_t* e_mat_out, double* err_out, hipStream_t st);
@@ -136,6 +183,13 @@ hipError_t launch_lnz_moments(const double* lng, int N, int e0, int nE, int m0, 
                               const double* beta, const double* h, int64_t G, const double* lnz,
                               const double* gout, double* mom, double* gbeta, double* gh,
                               hipStream_t st);
+hipError_t launch_lnz_second(const double* lng, int N, int e0, int nE, int m0, int nM, const double* beta,
+                             const double* h, int64_t G, const double* lnz, const double* gout, const double* up_b,
+                             const double* up_h, double* d_go, double* d_b, double* d_h, hipStream_t st);
+hipError_t launch_lnz_grid_second(const double* lng, int N, int e0, int nE, int m0, int nM, const double* beta,
+                                  int64_t nB, const double* h, int64_t nH, const double* lnz, const double* gout,
+                                  const double* up_b, const double* up_h, double* A, double* u1, double* u2,
+                                  double* tb, double* th, double* d_go, double* d_b, double* d_h, hipStream_t st);
 hipError_t launch_lnz_grad_lng(const double* lng, int N, int e0, int nE, int m0, int nM,
                                const double* beta, const double* h, int64_t G, const double* lnz,
                                const double* grad_out, double* grad_lng, hipStream_t st);

@@ -192,13 +192,25 @@ __device__ __forceinline__ int win_dist(int e, int lo, int hi) {
     return e < lo ? lo - e : (e > hi ? e - hi : 0);
 }
 
+// Distance in bins from (e, m) to the window: in the split coordinate, or the
+// sum of both coordinates' distances for windows in both.
+__device__ __forceinline__ int window_distance(int split, const WDesc& d, int e, int m) {
+    if (split == 0) return win_dist(e, d.lo, d.hi);
+    if (split == 1) return win_dist(m, d.lo, d.hi);
+    return win_dist(e, d.lo, d.hi) + win_dist(m, d.mlo, d.mhi);
+}
+
+__device__ __forceinline__ bool in_window(int split, const WDesc& d, int e, int m) {
+    return window_distance(split, d, e, m) == 0;
+}
+
 __global__ void k_entry(DevState S, int64_t cap) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= S.n_walk) return;
     const WDesc d = S.wd[g];
     const PDesc P = S.pd[d.prob];
     int e = S.e[g], m = S.m[g];
-    int dist = win_dist(P.split ? m : e, d.lo, d.hi);  // distance in the split coordinate
+    int dist = window_distance(P.split, d, e, m);
     if (dist == 0) return;
     const int L = P.L, rw = P.row_words, K = P.K;
     uint32_t* sp = S.spins + d.spin_off;
@@ -218,7 +230,7 @@ __global__ void k_entry(DevState S, int64_t cap) {
                            (gbit(sp, rw, r == L - 1 ? 0 : r + 1, c) ^ bc);
         const int e2 = e + 2 - static_cast<int>(k);
         const int m2 = m + 1 - 2 * static_cast<int>(bc);
-        const int dist2 = win_dist(P.split ? m2 : e2, d.lo, d.hi);
+        const int dist2 = window_distance(P.split, d, e2, m2);
         const bool acc = dist2 <= dist ||
                          accept_move(-static_cast<int64_t>(4 * (dist2 - dist)) * (static_cast<int64_t>(1) << K),
                                      uw, K);
@@ -244,13 +256,19 @@ __global__ void k_entry(DevState S, int64_t cap) {
 // exp_neg evaluated.  Every path gives u < exp_neg(x) exactly.  The uniform
 // (u and its float rounding uf) is formed before the gathered ln g arrives,
 // and the filter has no branches: only the rare near-tie branches.
-__device__ __forceinline__ bool accept_pre(int64_t delta, double u, float uf, int K) {
+__device__ __forceinline__ bool accept_pre(int64_t delta, double u, float uf, int K, bool& exact_path) {
     const double x = ldexp(static_cast<double>(delta), -K);
     const float a = __builtin_amdgcn_exp2f(static_cast<float>(x) * 1.44269504f);
     bool acc = delta >= 0 || uf < a * 0.9999f;
     const bool rej = delta <= -(static_cast<int64_t>(23) << K) || uf > a * 1.0001f;
-    if (!acc && !rej) acc = u < exp_neg(x);
+    exact_path = !acc && !rej;
+    if (exact_path) acc = u < exp_neg(x);
     return acc;
+}
+
+__device__ __forceinline__ bool accept_pre(int64_t delta, double u, float uf, int K) {
+    bool unused;
+    return accept_pre(delta, u, uf, K, unused);
 }
 
 // First and second halves of a Philox4x32-10 evaluation, so that the next
@@ -299,8 +317,10 @@ __device__ __forceinline__ void pin(NoRounds&, int64_t& v, float& f) {
 // n_trials Wang-Landau trials (Eq. 1) for walker g (lane `lane` of a
 // workgroup of WG lanes).  Its spins sit in LDS column `lane`; no lane touches
 // another's data, so there are no barriers.  The bin the walker occupies is
-// held in registers and written back when the walker leaves it.
-template <typename RowT, int SPLIT>
+// held in registers and written back when the walker leaves it.  SPLIT: the
+// window coordinate (0 energy, 1 magnetization, 2 both); BAND: band addressing
+// of energy-window tables.
+template <typename RowT, int SPLIT, int BAND>
 __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int lane, int WG, int64_t g,
                                              int64_t n_trials) {
     const WDesc d = S.wd[g];
@@ -310,8 +330,7 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
     const int L = P.L, K = P.K, rw = P.row_words;
     const int s = S.stage[d.gwin];
     const int64_t inc = static_cast<int64_t>(1) << (K - s);
-    const int lo = d.lo, hi = d.hi;
-    const uint32_t ntm = d.ntm;
+    const int lo = d.lo, hi = d.hi, mlo = d.mlo, mhi = d.mhi;
     const uint64_t seed = P.seed;
     const uint32_t gid = static_cast<uint32_t>(d.gid);
     int64_t* tab = S.lng + d.table_off;
@@ -329,8 +348,7 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
     int e = S.e[g], m = S.m[g];
     int64_t t = S.t[g];
     uint32_t nseen = S.nseen[g];
-    // table origin: rows e - lo by all m (energy windows), or all e by m - lo
-    uint32_t cur = SPLIT ? tile_index(e, m - lo, ntm) : tile_index(e - lo, m, ntm);
+    uint32_t cur = table_index<BAND>(d, e, m);
     int64_t lng_cur = tab[cur];
 
     // One trial with the words (sw, uw) of its Philox block; `q` (a PhiloxRun)
@@ -353,11 +371,12 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
                            ((static_cast<uint32_t>(rowd >> c) & 1u) ^ bc);
         const int e2 = e + 2 - static_cast<int>(k);       // dE = 8 - 4k
         const int m2 = m + 1 - 2 * static_cast<int>(bc);  // dM = -2 s
-        const int x2 = SPLIT ? m2 : e2;  // the coordinate the windows split
-        const bool in = x2 >= lo && x2 <= hi;
-        // gather unconditionally (a bin of the current row, or column, when out of the window)
-        const uint32_t idx2 = SPLIT ? tile_index(e2, (in ? m2 : m) - lo, ntm)
-                                    : tile_index((in ? e2 : e) - lo, m2, ntm);
+        bool in;
+        if constexpr (SPLIT == 0) in = e2 >= lo && e2 <= hi;
+        else if constexpr (SPLIT == 1) in = m2 >= lo && m2 <= hi;
+        else in = e2 >= lo && e2 <= hi && m2 >= mlo && m2 <= mhi;
+        // gather unconditionally (the current bin when the proposal leaves the window)
+        const uint32_t idx2 = in ? table_index<BAND>(d, e2, m2) : cur;
         int64_t lng2 = tab[idx2];
         const double u = __dmul_rn(__dadd_rn(static_cast<double>(uw), 0.5), 1.0 / 4294967296.0);
         float uf = static_cast<float>(u);
@@ -423,7 +442,7 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
 // walkers in flight and so the set of table lines competing for the L2; the
 // tile-to-workgroup map is the same at every launch, so a walker stays on the
 // same XCD.
-template <typename RowT, int SPLIT>
+template <typename RowT, int SPLIT, int BAND>
 __global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int64_t g_count,
                                                int64_t n_trials, int wpw) {
     extern __shared__ unsigned char lds_raw[];
@@ -437,7 +456,7 @@ __global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int6
     const int64_t n_tiles = (g_count + per - 1) / per;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t gi = tile * per + wave * wpw + wl;
-        if (wl < wpw && gi < g_count) sweep_walker<RowT, SPLIT>(S, lds, lane, WG, g_begin + gi, n_trials);
+        if (wl < wpw && gi < g_count) sweep_walker<RowT, SPLIT, BAND>(S, lds, lane, WG, g_begin + gi, n_trials);
     }
 }
 
@@ -649,8 +668,9 @@ __global__ void __launch_bounds__(256) k_snapshot(DevState S) {
 }
 
 // ------------------------------------------------------------------ exchange
-// One workgroup per adjacent window pair (w, w+1) of a problem; pairs with
-// w = r (mod 2) act in round r (Sec. 2, Eq. 2).  Lane 0 draws the random
+// One workgroup per neighbouring window pair (w, v) of a problem; pairs whose
+// lower window w has index = r (mod 2) along their direction act in round r
+// (Sec. 2, Eq. 2).  Lane 0 draws the random
 // matching (Fisher-Yates from the XPERM stream), tests that both
 // configurations lie in the overlap, and accepts with
 // min[1, g_A(X) g_B(Y) / (g_A(Y) g_B(X))]; then the workgroup swaps the
@@ -660,12 +680,16 @@ __global__ void __launch_bounds__(64) k_exchange(DevState S) {
     __shared__ int32_t acc_a[256], acc_b[256];
     __shared__ int n_acc;
     const PairDesc pr = S.pairs[blockIdx.x];
-    const int p = pr.prob, w = pr.w;
+    const int p = pr.prob, w = pr.wa, v = pr.wb;
     if (!S.xon[p]) return;
     const int64_t r = S.xr[p];
-    if ((w & 1) != static_cast<int>(r & 1)) return;
+    // round r: pairs whose lower window has index along its direction = r (mod 2);
+    // with windows in both coordinates, pairs along E on rounds with bit 1 of r
+    // clear and along M on the others
+    if ((pr.along & 1) != static_cast<int>(r & 1)) return;
+    if (pr.dir != static_cast<int>((r >> 1) & 1) && S.pd[p].split == 2) return;
     const PDesc P = S.pd[p];
-    if (S.wdone[P.win_off + w] || S.wdone[P.win_off + w + 1]) return;  // a finished window does not exchange
+    if (S.wdone[P.win_off + w] || S.wdone[P.win_off + v]) return;  // a finished window does not exchange
     const int W = P.W;
     if (threadIdx.x == 0) {
         const uint32_t r_lo = static_cast<uint32_t>(r), r_hi = static_cast<uint32_t>(static_cast<uint64_t>(r) >> 32);
@@ -681,19 +705,21 @@ __global__ void __launch_bounds__(64) k_exchange(DevState S) {
         int n = 0;
         for (int a = 0; a < W; ++a) {
             const int A = P.walker_off + w * W + a;
-            const int B = P.walker_off + (w + 1) * W + perm[a];
+            const int B = P.walker_off + v * W + perm[a];
             const WDesc dA = S.wd[A], dB = S.wd[B];
             const int eA = S.e[A], mA = S.m[A], eB = S.e[B], mB = S.m[B];
-            const int xA = P.split ? mA : eA, xB = P.split ? mB : eB;  // split coordinate
-            if (xA < dB.lo || xA > dB.hi || xB < dA.lo || xB > dA.hi) continue;
+            if (!in_window(P.split, dB, eA, mA) || !in_window(P.split, dA, eB, mB)) continue;
             const int64_t* tA = S.lng + dA.table_off;
             const int64_t* tB = S.lng + dB.table_off;
-            // table origins: (lo, 0) for energy windows, (0, lo) for magnetization windows
-            const int eoA = P.split ? 0 : dA.lo, moA = P.split ? dA.lo : 0;
-            const int eoB = P.split ? 0 : dB.lo, moB = P.split ? dB.lo : 0;
-            const int64_t delta =
-                tA[tile_index(eA - eoA, mA - moA, dA.ntm)] - tA[tile_index(eB - eoA, mB - moA, dA.ntm)] +
-                tB[tile_index(eB - eoB, mB - moB, dB.ntm)] - tB[tile_index(eA - eoB, mA - moB, dB.ntm)];
+            // both configurations are states of both windows, so every bin below is stored;
+            // a bin that is not would be a layout error, reported instead of read
+            const int64_t iAX = table_index_or_none(dA, eA, mA), iAY = table_index_or_none(dA, eB, mB);
+            const int64_t iBY = table_index_or_none(dB, eB, mB), iBX = table_index_or_none(dB, eA, mA);
+            if (iAX < 0 || iAY < 0 || iBY < 0 || iBX < 0) {
+                atomicOr(&S.counters[1], ERR_LAYOUT);
+                continue;
+            }
+            const int64_t delta = tA[iAX] - tA[iAY] + tB[iBY] - tB[iBX];
             const Words4 b = philox4x32_10(P.seed, r_lo, r_hi, static_cast<uint32_t>(w),
                                            (TAG_XACC << 24) | static_cast<uint32_t>(a));
             if (accept_move(delta, b.x, P.K)) {
@@ -721,6 +747,51 @@ __global__ void __launch_bounds__(64) k_exchange(DevState S) {
     }
 }
 
+// ------------------------------------------------------------------ self-check
+// Not part of the sampling path: the sweep's acceptance (accept_pre, float
+// filter plus exact fallback) against the specified comparison (accept_move)
+// on n trial pairs (delta, u word) placed near the decision boundary.  Pair i
+// draws delta uniformly from [-23 2^K, -1] and a relative offset r in
+// [-rel, rel] from Philox block (i, 0, 0, 5 << 24) of `seed`, and takes the
+// word w nearest to exp(delta 2^-K) (1 + r) 2^32 - 1/2; every eighth pair
+// takes instead the word next to the boundary itself (offset -2 .. 2 words),
+// where the exact path must decide.  counts[0] += disagreements, counts[1] +=
+// pairs decided by the exact path, counts[2] += acceptances; the first n_samp
+// pairs and decisions are written out for a check against the CPU.
+__global__ void k_accept_check(int K, uint64_t seed, int64_t n, double rel, unsigned long long* counts,
+                               int64_t* sd, uint32_t* su, int32_t* sdec, int n_samp) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Words4 b = philox4x32_10(seed, static_cast<uint32_t>(i), static_cast<uint32_t>(static_cast<uint64_t>(i) >> 32),
+                                   0u, 5u << 24);
+    const uint64_t span = static_cast<uint64_t>(23) << K;
+    const uint64_t r64 = (static_cast<uint64_t>(b.x) << 32) | b.y;
+    const int64_t delta = -static_cast<int64_t>(r64 % span) - 1;
+    const double x = ldexp(static_cast<double>(delta), -K);
+    const double ex = exp_neg(x) * 4294967296.0;
+    double target;
+    if ((i & 7) == 7) {
+        target = floor(ex - 0.5) + static_cast<double>(static_cast<int>(b.z % 5u) - 2);
+    } else {
+        const double off = (static_cast<double>(b.z) / 4294967296.0 * 2.0 - 1.0) * rel;
+        target = floor(ex * (1.0 + off) - 0.5);
+    }
+    target = fmin(fmax(target, 0.0), 4294967295.0);
+    const uint32_t w = static_cast<uint32_t>(target);
+    const double u = __dmul_rn(__dadd_rn(static_cast<double>(w), 0.5), 1.0 / 4294967296.0);
+    bool exact_path = false;
+    const bool fast = accept_pre(delta, u, static_cast<float>(u), K, exact_path);
+    const bool spec = accept_move(delta, w, K);
+    if (fast != spec) atomicAdd(&counts[0], 1ull);
+    if (exact_path) atomicAdd(&counts[1], 1ull);
+    if (spec) atomicAdd(&counts[2], 1ull);
+    if (i < n_samp) {
+        sd[i] = delta;
+        su[i] = w;
+        sdec[i] = fast ? 1 : 0;
+    }
+}
+
 int blocks_for(int64_t n, int per) { return static_cast<int>((n + per - 1) / per); }
 
 }  // namespace
@@ -744,29 +815,44 @@ hipError_t launch_entry(const DevState& S, int64_t cap, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <typename RowT>
+void launch_sweep_t(int split, int band, dim3 grid, dim3 wg, size_t lds, hipStream_t st, const DevState& S,
+                    int64_t g_begin, int64_t g_count, int64_t n_trials, int wpw) {
+    if (split == 0 && band)
+        hipLaunchKernelGGL((k_sweep<RowT, 0, 1>), grid, wg, lds, st, S, g_begin, g_count, n_trials, wpw);
+    else if (split == 0)
+        hipLaunchKernelGGL((k_sweep<RowT, 0, 0>), grid, wg, lds, st, S, g_begin, g_count, n_trials, wpw);
+    else if (split == 1)
+        hipLaunchKernelGGL((k_sweep<RowT, 1, 0>), grid, wg, lds, st, S, g_begin, g_count, n_trials, wpw);
+    else
+        hipLaunchKernelGGL((k_sweep<RowT, 2, 0>), grid, wg, lds, st, S, g_begin, g_count, n_trials, wpw);
+}
+
 hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int64_t n_trials,
-                        int l_max, int wg, int max_grid, int wpw, int split, hipStream_t st) {
+                        int l_max, int wg, int max_grid, int wpw, int split, int layout, hipStream_t st) {
     if (g_count <= 0 || n_trials <= 0) return hipSuccess;
     if (wpw <= 0 || wpw > 64) wpw = 64;
     int grid = blocks_for(g_count, (wg / 64) * wpw);
     if (max_grid > 0 && grid > max_grid) grid = max_grid;
     const size_t lds = static_cast<size_t>(l_max) * wg * (l_max <= 32 ? sizeof(uint32_t) : sizeof(uint64_t));
-    if (l_max <= 32 && !split)
-        hipLaunchKernelGGL((k_sweep<uint32_t, 0>), dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
-    else if (!split)
-        hipLaunchKernelGGL((k_sweep<uint64_t, 0>), dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
-    else if (l_max <= 32)
-        hipLaunchKernelGGL((k_sweep<uint32_t, 1>), dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
+    // band addressing applies to energy windows only (magnetization windows keep dense addressing)
+    const int band = layout == LAYOUT_BAND && split == 0;
+    if (l_max <= 32)
+        launch_sweep_t<uint32_t>(split, band, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
     else
-        hipLaunchKernelGGL((k_sweep<uint64_t, 1>), dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
+        launch_sweep_t<uint64_t>(split, band, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
     return hipGetLastError();
 }
 
 hipError_t sweep_setup() {
-    const void* fns[4] = {reinterpret_cast<const void*>(&k_sweep<uint32_t, 0>),
-                          reinterpret_cast<const void*>(&k_sweep<uint64_t, 0>),
-                          reinterpret_cast<const void*>(&k_sweep<uint32_t, 1>),
-                          reinterpret_cast<const void*>(&k_sweep<uint64_t, 1>)};
+    const void* fns[8] = {reinterpret_cast<const void*>(&k_sweep<uint32_t, 0, 0>),
+                          reinterpret_cast<const void*>(&k_sweep<uint32_t, 0, 1>),
+                          reinterpret_cast<const void*>(&k_sweep<uint32_t, 1, 0>),
+                          reinterpret_cast<const void*>(&k_sweep<uint32_t, 2, 0>),
+                          reinterpret_cast<const void*>(&k_sweep<uint64_t, 0, 0>),
+                          reinterpret_cast<const void*>(&k_sweep<uint64_t, 0, 1>),
+                          reinterpret_cast<const void*>(&k_sweep<uint64_t, 1, 0>),
+                          reinterpret_cast<const void*>(&k_sweep<uint64_t, 2, 0>)};
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
@@ -793,6 +879,14 @@ hipError_t launch_average(const DevState& S, hipStream_t st) {
 hipError_t launch_snapshot(const DevState& S, hipStream_t st) {
     if (S.n_walk == 0) return hipSuccess;
     hipLaunchKernelGGL(k_snapshot, dim3(static_cast<unsigned>(S.n_walk)), dim3(256), 0, st, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_accept_check(int K, uint64_t seed, int64_t n, double rel, unsigned long long* counts, int64_t* sd,
+                               uint32_t* su, int32_t* sdec, int n_samp, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_accept_check, dim3(blocks_for(n, 256)), dim3(256), 0, st, K, seed, n, rel, counts, sd, su,
+                       sdec, n_samp);
     return hipGetLastError();
 }
 

@@ -139,3 +139,37 @@ def test_full_size_grid_on_32x32_sampled():
     lz0 = Z.lnz(lng, b[::256], 0.0 * b[::256])
     expect = np.repeat(lz0, 256) + N * np.log(np.cosh(b * h))
     assert np.max(np.abs(z - expect)) < 1e-9 * np.max(np.abs(expect))
+
+
+def test_second_order_entry_point_against_oracle():
+    """rewl_lnz_backward2 (the backward of the first-order products, in HIP) against the oracle's
+    Hessian products, with NULL upstream meaning zeros."""
+    torch, R = _torch()
+    lng, N = _synthetic(8)
+    lng = lng + np.random.default_rng(2).normal(0, 0.1, lng.shape)
+    b, h = _grid(5, 4)
+    rng = np.random.default_rng(5)
+    g, a, c = rng.uniform(0.5, 1.5, b.size), rng.normal(size=b.size), rng.normal(size=b.size)
+    T = lambda x: torch.tensor(x, device="cuda")
+    dl, db, dh = T(lng), T(b), T(h)
+    z = R.lnz_forward(dl, db, dh, N)
+    for aa, cc in ((a, c), (a, None), (None, c)):
+        got = R.lnz_second(dl, db, dh, z, T(g), None if aa is None else T(aa), None if cc is None else T(cc), N)
+        ref = Z.second(lng, b, h, g, aa, cc)
+        for x, y in zip(got, ref):
+            x = x.cpu().numpy()
+            assert np.allclose(x, y, rtol=1e-8, atol=1e-8 * N), np.max(np.abs(x - y))
+
+
+def test_double_backward_through_lng_is_refused():
+    torch, R = _torch()
+    LnZ = R.LnZ()
+    lng, N = _synthetic(4)
+    dl = torch.tensor(lng, device="cuda", requires_grad=True)
+    db = torch.tensor([0.4, 0.5], dtype=torch.float64, device="cuda", requires_grad=True)
+    dh = torch.tensor([0.1, -0.1], dtype=torch.float64, device="cuda", requires_grad=True)
+    z = LnZ.apply(dl, db, dh, N)
+    torch.autograd.grad(z.sum(), (dl, db, dh))            # first order is fine
+    z = LnZ.apply(dl, db, dh, N)
+    with pytest.raises(RuntimeError, match="ln g"):
+        torch.autograd.grad(z.sum(), (dl, db, dh), create_graph=True)

@@ -168,3 +168,27 @@ def test_full_size_grid_32x32():
     expect = lz0[:, None] + N * np.log(np.cosh(b[:, None] * h[None, :]))
     assert np.max(np.abs(z - expect)) < 1e-9 * np.max(np.abs(expect))
     assert np.allclose(mom[..., 3], N / np.cosh(b[:, None] * h[None, :]) ** 2, rtol=1e-8)
+
+
+def test_grid_second_order_entry_point_against_oracle():
+    """rewl_lnz_grid_backward2: per-point d grad_out and the row / column sums of the Hessian products
+    (the reductions run on the device), against the oracle evaluated point by point."""
+    torch, R = _torch()
+    lng, N = _tables()[2]
+    b, h = np.linspace(0.2, 0.9, 11), np.linspace(-0.4, 0.5, 7)
+    rng = np.random.default_rng(9)
+    g = rng.uniform(0.5, 1.5, (11, 7))
+    a, c = rng.normal(size=11), rng.normal(size=7)
+    T = lambda x: torch.tensor(x, device="cuda")
+    dl, db, dh = T(lng), T(b), T(h)
+    z = R.lnz_grid_forward(dl, db, dh, N)
+    B, H = np.meshgrid(b, h, indexing="ij")
+    for aa, cc in ((a, c), (a, None), (None, c)):
+        d_go, d_b, d_h = R.lnz_grid_second(dl, db, dh, z, T(g), None if aa is None else T(aa),
+                                           None if cc is None else T(cc), N)
+        A = np.zeros_like(B) if aa is None else np.broadcast_to(aa[:, None], B.shape)
+        Cc = np.zeros_like(B) if cc is None else np.broadcast_to(cc[None, :], B.shape)
+        r_go, r_b, r_h = Z.second(lng, B, H, g, A, Cc)
+        assert np.allclose(d_go.cpu().numpy(), r_go, rtol=1e-8, atol=1e-8 * N)
+        assert np.allclose(d_b.cpu().numpy(), r_b.sum(1), rtol=1e-8, atol=1e-8 * N)
+        assert np.allclose(d_h.cpu().numpy(), r_h.sum(0), rtol=1e-8, atol=1e-8 * N)

@@ -25,8 +25,9 @@ def _R():
 
 
 def _oracle_of(p):
+    mw = (p.m_windows, p.m_overlap) if p.split == 2 else None
     o = OracleREWL(p.L, p.n_windows, p.overlap, p.walkers_per_window, p.k_final, p.flat, p.interval,
-                   p.seed, p.init, sync=p.stage_sync)
+                   p.seed, p.init, sync=p.stage_sync, split=p.split, m_windows=mw)
     o.init()
     return o
 
@@ -52,7 +53,8 @@ def compare(plan, pi, orc, tables=True, walkers=None):
     info = orc.info()
     assert int(q["stage"][pi]) == info["stage"] and bool(q["done"][pi]) == info["done"], (q, info)
     qw = plan.query_windows(pi)
-    for w in range(p.n_windows):
+    assert plan.windows_of[pi] == orc.n_windows
+    for w in range(orc.n_windows):
         assert (int(qw["stage"][w]), bool(qw["done"][w])) == orc.window_state(w), (pi, w)
 
 

@@ -13,7 +13,9 @@ def _probs(R, n, **kw):
     return [R.Problem(seed=s, **base) for s in range(n)]
 
 
-def test_autotune_restores_state_and_keeps_results():
+def test_autotune_runs_the_plan_and_keeps_results():
+    """The autotuner times its candidates on real intervals of the plan (no copy of the buffers):
+    afterwards the plan has advanced by the intervals it ran, exactly as under any fixed tuning."""
     R = _R()
     from paper_1508_02748_amd.tune import autotune
     probs = _probs(R, 300)
@@ -21,12 +23,15 @@ def test_autotune_restores_state_and_keeps_results():
     plan = R.Plan(probs, R.Tuning(graph_intervals=2))
     plan.init()
     plan.run(3)
-    best = autotune(plan, intervals=1, candidates=[(64, 0), (128, 2), (256, 4), (64, 8)], use_cache=False)
-    assert best.walkers_per_wg in (64, 128, 256)
+    best = autotune(plan, intervals=1, candidates=[(64, 0), (128, 2), (256, 4), (64, 8), (64, 0, 16)],
+                    use_cache=False, graph_lengths=(1, 3))
+    assert best.walkers_per_wg in (64, 128, 256) and best.graph_intervals in (1, 3)
+    ran = plan.tune_report["intervals_run"]
+    assert ran == 2 * 5 + 2 * 2 * (1 + 3)
     plan.run(3)
     for i in (0, 150, 299):
         o = _oracle_of(probs[i])
-        o.run(6)
+        o.run(6 + ran)
         compare(plan, i, o)
 
 

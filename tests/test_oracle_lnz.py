@@ -119,3 +119,23 @@ def test_lnz_of_the_exact_tables_against_onsager(L):
     for beta in (0.6, 0.8, 1.0):
         d = float(Z.lnz(lng, beta, 0.0)[0]) / N - _onsager(beta)
         assert abs(d - math.log(2.0) / N) < 1e-9, (L, beta, d)
+
+
+def test_second_order_products_against_finite_differences():
+    """Z.second is the Hessian of ln Z in (beta, h) applied to the upstream (a, c), times g, plus the
+    gradient dotted with (a, c); every entry checked against finite differences of ln Z itself, so a
+    dropped cross term, a wrong power of beta or a swapped upstream fails."""
+    lng, N = _synthetic(4)
+    lng = lng + np.random.default_rng(3).normal(0, 0.3, lng.shape)
+    f = lambda bb, hh: Z.lnz(lng, bb, hh)[0]
+    d, dd = 1e-5, 1e-4
+    for b, h, g, a, c in [(0.3, 0.2, 1.3, 0.7, -0.4), (0.6, -0.4, 0.5, -1.1, 0.9), (0.44, 0.0, 2.0, 0.0, 1.0)]:
+        gb = (f(b + d, h) - f(b - d, h)) / (2 * d)
+        gh = (f(b, h + d) - f(b, h - d)) / (2 * d)
+        gbb = (f(b + dd, h) - 2 * f(b, h) + f(b - dd, h)) / dd ** 2
+        ghh = (f(b, h + dd) - 2 * f(b, h) + f(b, h - dd)) / dd ** 2
+        gbh = (f(b + dd, h + dd) - f(b + dd, h - dd) - f(b - dd, h + dd) + f(b - dd, h - dd)) / (4 * dd * dd)
+        d_go, d_b, d_h = Z.second(lng, b, h, g, a, c)
+        assert abs(d_go[0] - (a * gb + c * gh)) < 1e-6 * max(1, abs(d_go[0]))
+        assert abs(d_b[0] - g * (a * gbb + c * gbh)) < 2e-3 * max(1, abs(d_b[0]))
+        assert abs(d_h[0] - g * (a * gbh + c * ghh)) < 2e-3 * max(1, abs(d_h[0]))

@@ -241,19 +241,30 @@ rewl_status rewl_read_walker(rewl_plan* plan, int32_t prob, int32_t w, int32_t a
  * over their overlap, at or above the previous matching point, ties to the
  * lowest E; the upper window is shifted by one constant to agree there and
  * Eq. (4) takes the lower window below E_mat and the upper from E_mat on.
+ * Other splits (the alternatives of Sec. 2) join in two steps: first the
+ * windows sharing one magnetization range, by energy as above, then these
+ * magnetization columns along M by the same rule on their marginals over E,
+ * ln g(M) = log sum_E g (the column below M_mat from the lower one).  A
+ * magnetization split is one window per column; an energy split one column.
  * norm 0: ln g(E = -2N) = ln 2 (the two ground states); 1: sum g = 2^N.
  * Device outputs: lng_out (N+1) x (N+1) float64 by (e, m), -inf where no
  * walker visited; lnge_out (N+1) the marginal ln g(E) of that table;
- * e_mat_out (nullable) n_windows - 1 matching energy bins; lng_err_out
- * (nullable) (N+1) x (N+1) error bars: per bin, the standard error of the
- * window average over the walkers that visited it (sqrt(sum (x_a - mean)^2 /
- * (n (n-1))) of the aligned values, i.e. the leave-one-walker-out jackknife
- * error with the alignment held fixed; Sec. 2 notes that several walkers per
- * window make error bars possible), taken from the window that supplies the
- * row in Eq. (4); NaN where fewer than two walkers visited.  `workspace` is
- * device memory of rewl_merge_workspace_size bytes.  Synchronises;
- * REWL_ESTATE when a window's walkers share no visited bin or two windows
- * have no usable matching point. */
+ * e_mat_out (nullable) the rewl_merge_points matching points: for
+ * one-coordinate splits the n_windows - 1 points of consecutive windows (E_mat,
+ * or M_mat for magnetization windows); for windows in both coordinates, per
+ * window the E_mat at which it starts in its column (-1 for the lowest
+ * window of a column), then the M_mat of every column but the first;
+ * lng_err_out (nullable) (N+1) x (N+1) error bars: per bin, the standard
+ * error of the window average over the walkers that visited it
+ * (sqrt(sum (x_a - mean)^2 / (n (n-1))) of the aligned values, i.e. the
+ * leave-one-walker-out jackknife error with the alignment held fixed; Sec. 2
+ * notes that several walkers per window make error bars possible), taken from
+ * the window that supplies the bin in Eq. (4); NaN where fewer than two
+ * walkers visited.  `workspace` is device memory of
+ * rewl_merge_workspace_size bytes.  Synchronises; REWL_ESTATE when a
+ * window's walkers share no visited bin or two pieces have no usable
+ * matching point. */
+rewl_status rewl_merge_points(const rewl_plan* plan, int32_t prob, int32_t* n_points);
 rewl_status rewl_merge_workspace_size(const rewl_plan* plan, int32_t prob, size_t* bytes);
 rewl_status rewl_merge_lng(rewl_plan* plan, int32_t prob, int32_t norm, void* workspace, size_t workspace_bytes,
                            double* lng_out, double* lnge_out, int32_t* e_mat_out, double* lng_err_out);

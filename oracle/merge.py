@@ -150,7 +150,7 @@ def merge_m(pieces, N, norm="ground", errs=None):
     error table])."""
     tp = [(lo, hi, np.ascontiguousarray(t.T)) for lo, hi, t in pieces]
     te = None if errs is None else [np.ascontiguousarray(e.T) for e in errs]
-    out = merge(tp, N, "sum", te)
+    out = merge(tp, N, None, te)
     joint = normalise(np.ascontiguousarray(out[0].T), N, norm)
     res = (joint, marginal(joint), out[2])
     if errs is None:
@@ -158,7 +158,7 @@ def merge_m(pieces, N, norm="ground", errs=None):
     return res + (np.ascontiguousarray(out[3].T),)
 
 
-def merge_2d(pieces, N, norm="ground"):
+def merge_2d(pieces, N, norm="ground", errs=None):
     """Join rectangular (E, M) pieces (windows in both coordinates, Sec. 2 end).
 
     pieces: list of (e_lo, e_hi, m_lo, m_hi, lng) with lng float64 of shape
@@ -167,25 +167,38 @@ def merge_2d(pieces, N, norm="ground"):
     windows (E_mat from ln g(E) = log sum over the column's M), then the
     columns are joined along M (M_mat from ln g(M) = log sum over E).
     Returns (lng_joint (N+1, N+1), ln g(E), (E_mat lists per column, M_mat
-    list))."""
+    list)), and with ``errs`` (one error table per piece) also the joint error
+    table, each bin's error taken from the piece that supplies the bin."""
     cols = {}
-    for elo, ehi, mlo, mhi, t in pieces:
-        cols.setdefault((mlo, mhi), []).append((elo, ehi, t))
-    col_pieces, e_mats = [], []
+    for k, (elo, ehi, mlo, mhi, t) in enumerate(pieces):
+        cols.setdefault((mlo, mhi), []).append((elo, ehi, t, None if errs is None else errs[k]))
+    col_pieces, col_errs, e_mats = [], [], []
     for (mlo, mhi) in sorted(cols):
-        rows = []
-        for elo, ehi, t in sorted(cols[(mlo, mhi)], key=lambda x: x[0]):
+        rows, rerr = [], []
+        for elo, ehi, t, et in sorted(cols[(mlo, mhi)], key=lambda x: x[0]):
             f = np.full((ehi - elo + 1, N + 1), -np.inf)
             f[:, mlo:mhi + 1] = t
             rows.append((elo, ehi, f))
-        joint_c, _, em = merge(rows, N, "sum")
-        col_pieces.append((mlo, mhi, joint_c[:, mlo:mhi + 1]))
-        e_mats.append(em)
-    joint, marg, m_mats = merge_m(col_pieces, N, norm)
-    return joint, marg, (e_mats, m_mats)
+            if et is not None:
+                fe = np.full((ehi - elo + 1, N + 1), np.nan)
+                fe[:, mlo:mhi + 1] = et
+                rerr.append(fe)
+        out = merge(rows, N, None, rerr if errs is not None else None)
+        col_pieces.append((mlo, mhi, out[0][:, mlo:mhi + 1]))
+        if errs is not None:
+            col_errs.append(out[3][:, mlo:mhi + 1])
+        e_mats.append(out[2])
+    res = merge_m(col_pieces, N, norm, col_errs if errs is not None else None)
+    if errs is None:
+        return res[0], res[1], (e_mats, res[2])
+    return res[0], res[1], (e_mats, res[2]), res[3]
 
 
 def normalise(joint, N, norm="ground"):
+    """Fix the additive constant of ln g: "sum" (sum g = 2^N), "ground" (g(E = -2N) = 2) or None
+    (unchanged, for the intermediate joins of the two-coordinate merge)."""
+    if norm is None:
+        return joint
     if norm == "sum":
         return joint - _lse(joint[np.isfinite(joint)]) + N * math.log(2.0)
     if norm == "ground":
@@ -209,9 +222,7 @@ def merge_oracle_run(orc, norm="ground", with_err=False):
         pieces.append((lo, hi, avg))
         errs.append(err)
     if getattr(orc, "split", 0) == 2:
-        if with_err:
-            raise ValueError("error bars are not defined for the 2D join")
         rects = [orc.window_rect(w) + (p[2],) for w, p in enumerate(pieces)]
-        return merge_2d(rects, orc.N, norm)
+        return merge_2d(rects, orc.N, norm, errs if with_err else None)
     join = merge_m if getattr(orc, "split", 0) else merge
     return join(pieces, orc.N, norm, errs if with_err else None)

@@ -97,6 +97,7 @@ def lib():
             "rewl_sweep_times": ([P, P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
             "rewl_set_profile": ([P, C.c_int32], C.c_int),
             "rewl_merge_workspace_size": ([P, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
+            "rewl_merge_points": ([P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
             "rewl_set_tuning": ([P, C.POINTER(_Tuning)], C.c_int),
             "rewl_save_size": ([P, C.POINTER(C.c_size_t)], C.c_int),
             "rewl_save": ([P, P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
@@ -300,22 +301,26 @@ class Plan:
         return buf[:min(cap, n.value)].astype(np.float64)
 
     def merge(self, prob=0, norm="ground", with_err=False):
-        """Joint ln g(E, M) (device, float64, (N+1) x (N+1)), marginal ln g(E), E_mat list
-        [, error bars of the joint table (device, NaN below two walkers)]."""
+        """Joint ln g(E, M) (device, float64, (N+1) x (N+1)), marginal ln g(E), matching points
+        (rewl_merge_points: E_mat list, M_mat list for magnetization windows, per-window E_mat
+        then M_mat for windows in both coordinates) [, error bars of the joint table (device,
+        NaN below two walkers)]."""
         import torch
         p = self.problems[prob]
         nb = C.c_size_t()
         _check(lib().rewl_merge_workspace_size(self._h, prob, C.byref(nb)))
+        npts = C.c_int32()
+        _check(lib().rewl_merge_points(self._h, prob, C.byref(npts)))
         ws = torch.empty(max(1, nb.value), dtype=torch.uint8, device=self.device)
         joint = torch.empty((p.N + 1, p.N + 1), dtype=torch.float64, device=self.device)
         marg = torch.empty(p.N + 1, dtype=torch.float64, device=self.device)
-        emat = torch.zeros(max(1, p.n_windows - 1), dtype=torch.int32, device=self.device)
+        emat = torch.zeros(max(1, npts.value), dtype=torch.int32, device=self.device)
         err = torch.empty_like(joint) if with_err else None
         torch.cuda.current_stream(self.device).synchronize()
         _check(lib().rewl_merge_lng(self._h, prob, {"ground": 0, "sum": 1}[norm], C.c_void_p(ws.data_ptr()),
                                     nb.value, C.c_void_p(joint.data_ptr()), C.c_void_p(marg.data_ptr()),
                                     C.c_void_p(emat.data_ptr()), _ptr(err)))
-        em = [int(x) for x in emat.cpu()[:p.n_windows - 1]]
+        em = [int(x) for x in emat.cpu()[:npts.value]]
         return (joint, marg, em, err) if with_err else (joint, marg, em)
 
     def window(self, prob, w):

@@ -973,14 +973,25 @@ rewl_status rewl_lnz_backward2(const double* lng, int32_t N, int32_t e0, int32_t
     return REWL_OK;
 }
 
+}  // extern "C"
+
 // Tensor-product grids beta_i x h_j (factorised through the M columns).
-static rewl_status grid_check(const double* lng, int32_t N, int32_t e0, int32_t nE, int32_t m0, int32_t nM,
-                              const double* beta, int64_t nB, const double* h, int64_t nH) {
+rewl_status rewl::lnz_grid_check(const double* lng, int32_t N, int32_t e0, int32_t nE, int32_t m0, int32_t nM,
+                                 const double* beta, int64_t nB, const double* h, int64_t nH) {
     if (!lng || !beta || !h) return fail(REWL_EINVAL, "null pointer");
     if (N < 1 || nE < 1 || nM < 1 || e0 < 0 || m0 < 0 || e0 + nE > N + 1 || m0 + nM > N + 1)
         return fail(REWL_EINVAL, "bad reweighting geometry");
     if (nB < 0 || nH < 0 || nB > 65535 || nH > 256LL * 65535) return fail(REWL_EINVAL, "bad grid size");
     return REWL_OK;
+}
+
+rewl_status rewl::set_error(rewl_status st, const char* msg) { return fail(st, msg); }
+
+extern "C" {
+
+static rewl_status grid_check(const double* lng, int32_t N, int32_t e0, int32_t nE, int32_t m0, int32_t nM,
+                              const double* beta, int64_t nB, const double* h, int64_t nH) {
+    return lnz_grid_check(lng, N, e0, nE, m0, nM, beta, nB, h, nH);
 }
 
 static size_t grid_ws_bytes(int32_t nM, int64_t nB, int64_t nH) {
@@ -1106,48 +1117,112 @@ extern "C" rewl_status rewl_selfcheck_accept(int32_t K, uint64_t seed, int64_t n
 
 namespace {
 
+// Geometry of the merge of one problem: the windows grouped into magnetization
+// columns (see MergeGeo), and the workspace layout.
 struct MergeLayout {
     size_t bytes = 0;
     MergeGeo G{};
     int max_nE = 0;
+    int n_points = 0;
+    std::vector<int32_t> ints;    // the int region (flags cleared on the device)
+    std::vector<int64_t> avg_off;
+    size_t ints_at = 0, offs_at = 0;  // byte offsets of the two regions
 };
 
-rewl_status merge_layout(const rewl_plan* P, int32_t prob, char* base, MergeLayout& out) {
+rewl_status merge_layout(const rewl_plan* P, int32_t prob, MergeLayout& out) {
     if (prob < 0 || prob >= static_cast<int32_t>(P->pd.size())) return fail(REWL_EINVAL, "problem out of range");
     const PDesc& q = P->pd[prob];
-    if (q.nwin > MERGE_MAX_WINDOWS) return fail(REWL_EINVAL, "merge supports at most 256 windows");
-    const int64_t nM = q.N + 1;
-    int64_t o = 0;
+    const std::vector<Rect>& R = P->rect[prob];
+    const int nwin = q.nwin, N = q.N;
+    // columns: windows sharing one magnetization range, by m_lo, each by energy
+    std::vector<int> order(nwin);
+    for (int w = 0; w < nwin; ++w) order[w] = w;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (R[a].mlo != R[b].mlo) return R[a].mlo < R[b].mlo;
+        if (R[a].mhi != R[b].mhi) return R[a].mhi < R[b].mhi;
+        return R[a].elo < R[b].elo;
+    });
+    std::vector<int> col(nwin), first, count, cmlo, cmhi;
+    for (int k = 0; k < nwin; ++k) {
+        const Rect& r = R[order[k]];
+        if (k == 0 || r.mlo != cmlo.back() || r.mhi != cmhi.back()) {
+            first.push_back(k);
+            count.push_back(0);
+            cmlo.push_back(r.mlo);
+            cmhi.push_back(r.mhi);
+        }
+        count.back() += 1;
+        col[order[k]] = static_cast<int>(first.size()) - 1;
+    }
+    const int ncol = static_cast<int>(first.size());
     MergeGeo G{};
     G.prob = prob;
-    G.off_shift = o;
-    o += static_cast<int64_t>(q.nwin) * q.W;
-    G.off_marg = o;
-    o += static_cast<int64_t>(q.nwin) * nM;
-    G.off_mg = o;
-    o += nM;
-    G.off_pshift = o;
-    o += q.nwin;
-    G.off_cst = o;
-    o += 1;
+    G.nwin = nwin;
+    G.ncol = ncol;
+    G.W = q.W;
+    G.N = N;
+    G.K = q.K;
+    int64_t o = 0;
+    auto take = [&](int64_t n) {
+        const int64_t at = o;
+        o += n;
+        return at;
+    };
+    G.off_shift = take(static_cast<int64_t>(nwin) * q.W);
+    out.avg_off.assign(nwin, 0);
     int max_nE = 0;
-    for (int w = 0; w < q.nwin; ++w) {
-        const int nE = P->rect[prob][w].ehi - P->rect[prob][w].elo + 1;
-        max_nE = std::max(max_nE, nE);
-        G.off_avg[w] = o;
-        o += 2 * static_cast<int64_t>(nE) * nM;  // averages, then their standard errors
+    for (int w = 0; w < nwin; ++w) {
+        const int64_t nE = R[w].ehi - R[w].elo + 1, nM = R[w].mhi - R[w].mlo + 1;
+        max_nE = std::max<int>(max_nE, static_cast<int>(nE));
+        out.avg_off[w] = take(2 * nE * nM);  // averages, then their standard errors
     }
+    G.off_margA = take(static_cast<int64_t>(nwin) * (N + 1));
+    G.off_runA = take(static_cast<int64_t>(ncol) * (N + 1));
+    G.off_shiftA = take(nwin);
+    G.off_stageA = take(nwin);
+    G.off_margB = take(static_cast<int64_t>(ncol) * (N + 1));
+    G.off_runB = take(N + 1);
+    G.off_shiftB = take(ncol);
+    G.off_cst = take(1);
     const size_t dbl_bytes = align_up(static_cast<size_t>(o) * sizeof(double), 256);
-    // integer region (256-byte aligned): 4 flags (16 bytes, cleared with one
-    // 16-byte store), then the matching points
-    out.bytes = dbl_bytes + align_up(16 + static_cast<size_t>(q.nwin) * sizeof(int32_t), 256);
-    if (base) {  // sizes only when no workspace is given
-        G.ws = reinterpret_cast<double*>(base);
-        G.flags = reinterpret_cast<int32_t*>(base + dbl_bytes);
-        G.emat = G.flags + 4;
+    const size_t off_bytes = align_up(static_cast<size_t>(nwin) * sizeof(int64_t), 256);
+    int32_t io = 4;  // flags
+    auto itake = [&](int32_t n) {
+        const int32_t at = io;
+        io += n;
+        return at;
+    };
+    G.off_col = itake(nwin);
+    G.off_ematA = itake(nwin);
+    G.off_first = itake(ncol);
+    G.off_count = itake(ncol);
+    G.off_cmlo = itake(ncol);
+    G.off_cmhi = itake(ncol);
+    G.off_mmat = itake(ncol);
+    G.off_members = itake(nwin);
+    G.off_stage = itake(nwin);
+    G.off_rect = itake(4 * nwin);
+    out.ints.assign(io, 0);
+    for (int w = 0; w < nwin; ++w) {
+        out.ints[G.off_col + w] = col[w];
+        out.ints[G.off_members + w] = order[w];
+        out.ints[G.off_rect + 4 * w] = R[w].elo;
+        out.ints[G.off_rect + 4 * w + 1] = R[w].ehi;
+        out.ints[G.off_rect + 4 * w + 2] = R[w].mlo;
+        out.ints[G.off_rect + 4 * w + 3] = R[w].mhi;
     }
+    for (int c = 0; c < ncol; ++c) {
+        out.ints[G.off_first + c] = first[c];
+        out.ints[G.off_count + c] = count[c];
+        out.ints[G.off_cmlo + c] = cmlo[c];
+        out.ints[G.off_cmhi + c] = cmhi[c];
+    }
+    out.offs_at = dbl_bytes;
+    out.ints_at = dbl_bytes + off_bytes;
+    out.bytes = out.ints_at + align_up(static_cast<size_t>(io) * sizeof(int32_t), 256);
     out.G = G;
     out.max_nE = max_nE;
+    out.n_points = P->split == REWL_SPLIT_BOTH ? nwin + ncol - 1 : nwin - 1;
     return REWL_OK;
 }
 
@@ -1156,9 +1231,18 @@ rewl_status merge_layout(const rewl_plan* P, int32_t prob, char* base, MergeLayo
 extern "C" rewl_status rewl_merge_workspace_size(const rewl_plan* P, int32_t prob, size_t* bytes) {
     if (!P || !bytes) return fail(REWL_EINVAL, "null argument");
     MergeLayout ml;
-    rewl_status s = merge_layout(P, prob, nullptr, ml);
+    rewl_status s = merge_layout(P, prob, ml);
     if (s != REWL_OK) return s;
     *bytes = ml.bytes;
+    return REWL_OK;
+}
+
+extern "C" rewl_status rewl_merge_points(const rewl_plan* P, int32_t prob, int32_t* n_points) {
+    if (!P || !n_points) return fail(REWL_EINVAL, "null argument");
+    MergeLayout ml;
+    rewl_status s = merge_layout(P, prob, ml);
+    if (s != REWL_OK) return s;
+    *n_points = ml.n_points;
     return REWL_OK;
 }
 
@@ -1169,17 +1253,22 @@ extern "C" rewl_status rewl_merge_lng(rewl_plan* P, int32_t prob, int32_t norm, 
     if (!P->initialised) return fail(REWL_ESTATE, "rewl_init has not run");
     if (norm != 0 && norm != 1) return fail(REWL_EINVAL, "norm must be 0 (ground state) or 1 (sum)");
     if (!workspace || !lng_out || !lnge_out) return fail(REWL_EINVAL, "null device pointer");
-    if (P->split) return fail(REWL_EINVAL, "the device merge joins energy windows only");
     MergeLayout ml;
-    if ((s = merge_layout(P, prob, static_cast<char*>(workspace), ml)) != REWL_OK) return s;
+    if ((s = merge_layout(P, prob, ml)) != REWL_OK) return s;
     if (ws_bytes < ml.bytes) return fail(REWL_EINVAL, "workspace too small");
-    const PDesc& q = P->pd[prob];
-    HIPCHK(P, launch_zero(ml.G.flags, 16, P->stream), "merge flag clear");
-    HIPCHK(P, launch_merge(P->S, ml.G, q.N, q.nwin, ml.max_nE, norm, lng_out, lnge_out, e_mat_out, lng_err_out,
-                           P->stream),
-           "merge launch");
+    char* base = static_cast<char*>(workspace);
+    ml.G.ws = reinterpret_cast<double*>(base);
+    ml.G.avg_off = reinterpret_cast<int64_t*>(base + ml.offs_at);
+    ml.G.iws = reinterpret_cast<int32_t*>(base + ml.ints_at);
+    HIPCHK(P, hipMemcpyAsync(ml.G.avg_off, ml.avg_off.data(), ml.avg_off.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice, P->stream), "merge geometry upload");
+    HIPCHK(P, hipMemcpyAsync(ml.G.iws, ml.ints.data(), ml.ints.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                             P->stream), "merge geometry upload");
+    HIPCHK(P, launch_merge(P->S, ml.G, ml.max_nE, norm, lng_out, lnge_out, lng_err_out, P->stream), "merge launch");
+    if (e_mat_out && ml.n_points > 0)
+        HIPCHK(P, launch_merge_points(ml.G, P->split, e_mat_out, P->stream), "merge points launch");
     int32_t flags[4];
-    HIPCHK(P, hipMemcpyAsync(flags, ml.G.flags, 16, hipMemcpyDeviceToHost, P->stream), "merge flag read");
+    HIPCHK(P, hipMemcpyAsync(flags, ml.G.iws, 16, hipMemcpyDeviceToHost, P->stream), "merge flag read");
     HIPCHK(P, hipStreamSynchronize(P->stream), "merge sync");
     if (flags[0] == 1) return fail(REWL_ESTATE, "the walkers of a window share no visited bin");
     if (flags[0] == 2) return fail(REWL_ESTATE, "no matching point in the overlap of two windows");

@@ -141,21 +141,46 @@ struct DevState {
 
 enum : int32_t { ERR_OVERFLOW = 1, ERR_LAYOUT = 2 };
 
-// Workspace of the merge of one problem (offsets in doubles from ws).
-constexpr int MERGE_MAX_WINDOWS = 256;
+// Workspace of the merge of one problem.  The windows are joined in two
+// steps: first along E within each magnetization column (the windows sharing
+// one magnetization range, ordered by energy), then the columns along M.  An
+// energy split has one column holding every window; a magnetization split one
+// window per column.  Double offsets are from ws, int offsets from iws.
 struct MergeGeo {
-    int32_t prob;
+    int32_t prob, nwin, ncol, W, N, K;
     double* ws;
-    int64_t off_shift;   // n_windows * W alignment constants
-    int64_t off_marg;    // n_windows * (N + 1) window marginals (Eq. 3)
-    int64_t off_mg;      // N + 1: marginal of the pieces joined so far
-    int64_t off_pshift;  // n_windows additive constants of the pieces
-    int64_t off_cst;     // normalisation constant
-    int64_t off_avg[MERGE_MAX_WINDOWS];  // window-averaged tables, (hi-lo+1) x (N+1), each
-                                         // followed by its standard-error table
-    int32_t* emat;       // n_windows matching points (emat[0] = 0)
-    int32_t* flags;      // [0] != 0: no common bin (1) or no matching point (2)
+    int32_t* iws;
+    int64_t* avg_off;     // per window: offset (doubles) of its averaged table (rows e - e_lo,
+                          // columns m - m_lo), followed by the table's standard errors
+    int64_t off_shift;    // nwin * W walker alignment constants
+    int64_t off_margA;    // nwin * (N + 1): each window's marginal over M, as a function of e
+    int64_t off_runA;     // ncol * (N + 1): running marginal of each column's join
+    int64_t off_shiftA;   // nwin: additive constant of each window in its column
+    int64_t off_stageA;   // nwin: the same constants in column-member order (join scratch)
+    int64_t off_margB;    // ncol * (N + 1): each joined column's marginal over E, a function of m
+    int64_t off_runB;     // N + 1: running marginal of the join along M
+    int64_t off_shiftB;   // ncol: additive constant of each column
+    int64_t off_cst;      // normalisation constant
+    // int region: [0, 4) flags ([0] != 0: no common bin (1) or no matching point (2));
+    // then per window: column, E_mat where it starts within its column (its e_lo for
+    // the first); per column: first member (index into members), member count, m_lo,
+    // m_hi, M_mat where it starts (its m_lo for the first); members: windows by column
+    // then energy; join scratch (nwin); rectangles e_lo, e_hi, m_lo, m_hi per window
+    int32_t off_col, off_ematA, off_first, off_count, off_cmlo, off_cmhi, off_mmat, off_members, off_stage,
+        off_rect;
 };
+
+}  // namespace rewl
+
+#include "rewl.h"
+
+namespace rewl {
+
+// Host helpers shared by the C-ABI sources (rewl_host.cpp): argument checks of
+// the tensor-product reweighting, and recording an error message.
+rewl_status lnz_grid_check(const double* lng, int32_t N, int32_t e0, int32_t nE, int32_t m0, int32_t nM,
+                           const double* beta, int64_t nB, const double* h, int64_t nH);
+rewl_status set_error(rewl_status st, const char* msg);
 
 // Launchers (rewl_kernels.hip).  All enqueue on `st` and return the launch status.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
@@ -172,8 +197,9 @@ hipError_t launch_exchange(const DevState& S, hipStream_t st);
 hipError_t launch_accept_check(int K, uint64_t seed, int64_t n, double rel, unsigned long long* counts, int64_t* sd,
                                uint32_t* su, int32_t* sdec, int n_samp, hipStream_t st);
 
-hipError_t launch_merge(const DevState& S, const MergeGeo& G, int N, int nwin, int max_nE, int norm,
-                        double* lng_out, double* lnge_out, int32_t* e_mat_out, double* err_out, hipStream_t st);
+hipError_t launch_merge(const DevState& S, const MergeGeo& G, int max_nE, int norm, double* lng_out,
+                        double* lnge_out, double* err_out, hipStream_t st);
+hipError_t launch_merge_points(const MergeGeo& G, int split, int32_t* out, hipStream_t st);
 
 // Reweighting.
 hipError_t launch_lnz_forward(const double* lng, int N, int e0, int nE, int m0, int nM,

@@ -25,21 +25,38 @@ def _R():
     return R
 
 
-def _pair(R, p, n_intervals):
-    plan = R.Plan([p])
+def _pair(R, p, n_intervals, tuning=None):
+    plan = R.Plan([p], tuning)
     plan.init()
     plan.run(n_intervals)
+    mw = (p.m_windows, p.m_overlap) if p.split == 2 else None
     o = OracleREWL(p.L, p.n_windows, p.overlap, p.walkers_per_window, p.k_final, p.flat, p.interval,
-                   p.seed, p.init)
+                   p.seed, p.init, split=p.split, m_windows=mw)
     o.init()
     o.run(n_intervals)
     return plan, o
+
+
+def _points_2d(o, rem):
+    """The oracle's (E_mat lists per column, M_mat list) in the device's order: per window its E_mat
+    within its column (-1 for the column's lowest window), then the M_mats."""
+    e_mats, m_mats = rem
+    rects = [o.window_rect(w) for w in range(o.n_windows)]
+    cols = sorted({(r[2], r[3]) for r in rects})
+    out = [None] * o.n_windows
+    for c, key in enumerate(cols):
+        members = sorted((r[0], w) for w, r in enumerate(rects) if (r[2], r[3]) == key)
+        for k, (_, w) in enumerate(members):
+            out[w] = -1 if k == 0 else e_mats[c][k - 1]
+    return out + list(m_mats)
 
 
 def _check(plan, o, norm):
     j, g, em, err = plan.merge(0, norm, with_err=True)
     j, g, err = j.cpu().numpy(), g.cpu().numpy(), err.cpu().numpy()
     rj, rg, rem, rerr = MG.merge_oracle_run(o, norm, with_err=True)
+    if getattr(o, "split", 0) == 2:
+        rem = _points_2d(o, rem)
     assert em == rem, (em, rem)
     # error bars: NaN exactly where fewer than two walkers visited, else equal to ~1e-12
     assert (np.isnan(err) == np.isnan(rerr)).all()
@@ -79,3 +96,40 @@ def test_merge_single_window_4x4_full_run():
     mask = G > 0
     assert (np.isfinite(j) == mask).all()
     assert np.max(np.abs(j[mask] - np.log(G[mask]))) < 0.2
+
+
+@pytest.mark.parametrize("norm", ["ground", "sum"])
+def test_merge_magnetization_split_matches_oracle(norm):
+    """The join along M (M_mat from the marginals over E) of magnetization windows, dense and band."""
+    R = _R()
+    p = R.Problem(L=8, n_windows=3, overlap=(1, 2), walkers_per_window=2, k_final=8, interval=1000, seed=4,
+                  split=R.SPLIT_MAGNETIZATION)
+    for lay in (R.LAYOUT_DENSE, R.LAYOUT_BAND):
+        plan, o = _pair(R, p, 300, R.Tuning(table_layout=lay))
+        _check(plan, o, norm)
+
+
+def test_merge_16x16_magnetization_split():
+    R = _R()
+    p = R.Problem(L=16, n_windows=6, overlap=(1, 2), walkers_per_window=3, k_final=12, interval=10_000, seed=8,
+                  split=R.SPLIT_MAGNETIZATION)
+    plan, o = _pair(R, p, 150)
+    _check(plan, o, "sum")
+
+
+@pytest.mark.parametrize("norm", ["ground", "sum"])
+def test_merge_windows_in_both_coordinates(norm):
+    """The two-step join of rectangles: along E within each magnetization column, then the columns
+    along M; matching points, joint table, marginal and error bars against the oracle."""
+    R = _R()
+    p = R.Problem(L=8, n_windows=3, overlap=(1, 2), walkers_per_window=2, k_final=8, interval=1000, seed=6,
+                  split=R.SPLIT_BOTH, m_windows=3, m_overlap=(1, 2))
+    plan, o = _pair(R, p, 400)
+    _check(plan, o, norm)
+
+
+def test_merge_energy_band_layout():
+    R = _R()
+    p = R.Problem(L=16, n_windows=8, walkers_per_window=4, k_final=20, interval=10_000, seed=0)
+    plan, o = _pair(R, p, 120, R.Tuning(table_layout=R.LAYOUT_BAND))
+    _check(plan, o, "sum")

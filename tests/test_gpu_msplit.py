@@ -68,8 +68,6 @@ def test_msplit_plan_rules_on_host():
         R.Plan([R.Problem(L=8, split=E), R.Problem(L=8, split=M)])      # one split per plan
     plan = R.Plan([R.Problem(L=8, n_windows=2, overlap=(1, 2), walkers_per_window=2, split=M)])
     plan.init()
-    with pytest.raises(R.RewlError):
-        plan.merge(0)                                                   # device merge: energy windows only
     lo, hi = plan.window(0, 1)
     assert (lo, hi) == OracleREWL(8, 2, (1, 2), 2, 20, split=1).window(1)
     assert np.all([lo <= plan.walker(0, 1, a, tables=False)["m"] <= hi for a in range(2)])

@@ -322,6 +322,21 @@ rewl_status rewl_lnz_grid_forward(const double* lng, int32_t N, int32_t e0, int3
                                   const double* h, int64_t nH, void* workspace, size_t workspace_bytes,
                                   double* lnz, void* hip_stream);
 
+/* rewl_lnz_grid_forward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the workspace is a fixed array of REWL_NOALLOC_SCRATCH_BYTES of
+ * device memory that the library holds on each GPU it runs on until the
+ * process ends, so the call allocates nothing.  Needs nB * nM * 8 <=
+ * REWL_NOALLOC_SCRATCH_BYTES (REWL_EINVAL otherwise).  All calls on one GPU
+ * share that array: calls that overlap in time on one GPU (on different
+ * streams, or from several threads without ordering) race and may corrupt
+ * each other's results; calls ordered on one stream are safe.  Inputs,
+ * outputs and the result as for rewl_lnz_grid_forward (same kernels). */
+#define REWL_NOALLOC_SCRATCH_BYTES (64ull << 20)
+rewl_status rewl_lnz_grid_forward_noalloc(const double* lng, int32_t N, int32_t e0, int32_t nE,
+                                          int32_t m0, int32_t nM, const double* beta, int64_t nB,
+                                          const double* h, int64_t nH, double* lnz, void* hip_stream);
+
 /* Backward of rewl_lnz_grid_forward with the saved lnz (nB x nH) and upstream
  * grad_out (nB x nH, NULL = all ones).  grad_beta (nB) = sum_j g_ij <-E + h_j M>_ij
  * and grad_h (nH) = sum_i g_ij beta_i <M>_ij (both or neither); grad_lng

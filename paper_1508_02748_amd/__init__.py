@@ -88,6 +88,8 @@ def lib():
             "rewl_lnz_grid_workspace_size": ([C.c_int32, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)], C.c_int),
             "rewl_lnz_grid_forward": ([P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, C.c_int64,
                                        P, C.c_int64, P, C.c_size_t, P, P], C.c_int),
+            "rewl_lnz_grid_forward_noalloc": ([P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P,
+                                               C.c_int64, P, C.c_int64, P, P], C.c_int),
             "rewl_lnz_grid_backward": ([P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, C.c_int64,
                                         P, C.c_int64, P, P, P, C.c_size_t, P, P, P, P, P], C.c_int),
             "rewl_lnz_backward2": ([P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_int64,
@@ -434,6 +436,16 @@ def lnz_grid_forward(lng, beta, h, N, e0=0, m0=0):
     st = torch.cuda.current_stream(lng.device).cuda_stream
     _check(lib().rewl_lnz_grid_forward(_ptr(lng), *_geom(lng, N, e0, m0), _ptr(beta), beta.numel(), _ptr(h),
                                        h.numel(), _ptr(ws), nb, _ptr(out), C.c_void_p(st)))
+    return out
+
+
+def lnz_grid_forward_noalloc(lng, beta, h, out, N, e0=0, m0=0):
+    """ln Z on the grid into the caller's `out` (nB, nH) with no device allocation (the library's
+    fixed scratch array); every tensor must already be contiguous float64 on the device."""
+    import torch
+    st = torch.cuda.current_stream(lng.device).cuda_stream
+    _check(lib().rewl_lnz_grid_forward_noalloc(_ptr(lng), *_geom(lng, N, e0, m0), _ptr(beta), beta.numel(),
+                                               _ptr(h), h.numel(), _ptr(out), C.c_void_p(st)))
     return out
 
 

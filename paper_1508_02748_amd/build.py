@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librewl.so")
-SOURCES = ["rewl_kernels.hip", "lnz_kernels.hip", "merge_kernels.hip", "rewl_host.cpp"]
+SOURCES = ["rewl_kernels.hip", "lnz_kernels.hip", "merge_kernels.hip", "lnz_noalloc.hip", "rewl_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",

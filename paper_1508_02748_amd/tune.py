@@ -63,9 +63,15 @@ def _load_cache(path):
 
 
 def _shape_candidates(plan):
+    import torch
     cands = [(wg, gw, 0) for wg in WG_CANDIDATES for gw in GRID_CANDIDATES]
     if plan.n_walkers < SPREAD_BELOW:
         cands += [(64, 0, wpw) for wpw in WAVE_CANDIDATES if wpw * 1024 >= min(plan.n_walkers, 64 * 1024) // 4]
+        # the fewest lanes per wavefront that still keep at most one wavefront per SIMD
+        simds = 4 * torch.cuda.get_device_properties(plan.device).multi_processor_count
+        fit = -(-plan.n_walkers // simds)
+        if 1 <= fit < 64 and (64, 0, fit) not in cands:
+            cands.append((64, 0, fit))
     return cands
 
 

@@ -20,6 +20,17 @@ refining together (the paper) and with each window refining alone after
 averaging its walkers, compared in accuracy and in trials to finish.
 Replica r uses seed r (the second group uses seed 1000 + r).  Progress is
 printed every minute.
+
+  python tests/long_convergence.py --config c2 --replicas 64 --seconds 780 --decompose --out gpurun_out/dec
+
+--decompose runs for the given time and then splits the error of the joined
+marginal ln g(E) at every energy, per replica, into (1) the error of the window
+piece that supplies it, after the piece is shifted by the one constant that fits
+it best to the exact ln g(E) over its window (the piece error, Eq. 3), and (2)
+the difference between the joint's actual matching constants (E_mat, Eq. 4) and
+those best-fit constants (the join error), both after the same sum
+normalisation; reported as mean and standard error over the replicas at the two
+edge states E = -2N, +2N and at the next levels.
 """
 import argparse
 import json
@@ -56,6 +67,62 @@ def rel_diff(a, b):
     return 2.0 * np.abs(np.tanh(0.5 * (a - b)))
 
 
+def decompose(R, plan, probs, L, meta):
+    """Piece and join parts of each replica's marginal error (see the module notes)."""
+    from oracle import merge as MG
+    N = L * L
+    ex = exact_lnge(L)
+    ok = np.isfinite(ex) & (ex > 0)
+    lse = MG._lse
+    rows = []
+    for i, p in enumerate(probs):
+        pieces = []
+        for w in range(p.n_windows):
+            frags = [plan.walker(i, w, a)["lng"] for a in range(p.walkers_per_window)]
+            lo, hi = plan.window(i, w)
+            pieces.append((lo, hi, MG.window_average(frags, p.k_final)))
+        joint, marg, emats = MG.merge(pieces, N, "sum")
+        # best-fit constant of each piece's marginal against the exact ln g(E)
+        fit, resid = [], np.full(N + 1, np.nan)
+        for w, (lo, hi, t) in enumerate(pieces):
+            m = MG.marginal(t)
+            sel = np.isfinite(m) & ok[lo:hi + 1]
+            fit.append(float(np.mean(ex[lo:hi + 1][sel] - m[sel])))
+        # exact-shift join: every piece moved by its best-fit constant, rows taken from the same
+        # piece as in the actual join, then the same sum normalisation
+        bounds = [0] + list(emats) + [N + 1]
+        exact_join = np.full(N + 1, -np.inf)
+        for w, (lo, hi, t) in enumerate(pieces):
+            a, b = max(bounds[w], lo), min(bounds[w + 1], hi + 1)
+            exact_join[a:b] = MG.marginal(t)[a - lo:b - lo] + fit[w]
+            resid[a:b] = exact_join[a:b] - ex[a:b]
+        fin = np.isfinite(exact_join)
+        exact_join = exact_join - lse(exact_join[fin]) + N * math.log(2.0)
+        piece_err = exact_join - ex          # error with exact matching constants
+        total_err = marg - ex                # error of the actual joint
+        join_err = total_err - piece_err     # what the E_mat joins add
+        rows.append({"replica": i, "e_mat": [int(x) for x in emats],
+                     "total": {int(e): float(total_err[e]) for e in (0, 2, 3, N - 3, N - 2, N)},
+                     "piece": {int(e): float(piece_err[e]) for e in (0, 2, 3, N - 3, N - 2, N)},
+                     "join": {int(e): float(join_err[e]) for e in (0, 2, 3, N - 3, N - 2, N)},
+                     "piece_residual_edges": [float(resid[0]), float(resid[N])],
+                     "max_eps": float(np.max(np.abs(total_err[ok]) / ex[ok])),
+                     "max_eps_inner": float(np.max((np.abs(total_err[ok]) / ex[ok])[1:-1]))})
+    summ = {}
+    for part in ("total", "piece", "join"):
+        for e in (0, 2, 3, N - 3, N - 2, N):
+            v = np.array([r[part][e] for r in rows])
+            v = v[np.isfinite(v)]
+            summ[f"{part}@E={4 * e - 2 * N}"] = {"mean": float(v.mean()), "se": float(v.std(ddof=1) / np.sqrt(v.size)),
+                                                "rms": float(np.sqrt((v ** 2).mean())), "n": int(v.size)}
+    q = plan.query()
+    return {"replicas": len(probs), "stage_min_max": [int(q["stage"].min()), int(q["stage"].max())],
+            "trials_per_walker_min_max": [int(q["trials"].min()), int(q["trials"].max())],
+            "seconds": meta["seconds"], "summary": summ,
+            "max_eps_per_replica": [r["max_eps"] for r in rows],
+            "max_eps_inner_per_replica": [r["max_eps_inner"] for r in rows], "per_replica": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
@@ -65,6 +132,8 @@ def main():
     ap.add_argument("--resume", action="store_true")
     ap.add_argument("--evaluate-now", action="store_true",
                     help="compare the current (unfinished) state with the exact g(E) instead of running on")
+    ap.add_argument("--decompose", action="store_true",
+                    help="after --seconds, split the marginal's error into piece and join errors (see above)")
     args = ap.parse_args()
     import torch  # noqa: F401  (device memory for the plan)
     import paper_1508_02748_amd as R
@@ -102,6 +171,12 @@ def main():
                   f"{int(q['done'].sum())}/{len(probs)} done, {time.time() - t0:.0f}s", flush=True)
     meta["seconds"] += time.time() - t0
     q = plan.query()
+    if args.decompose:
+        res = decompose(R, plan, probs, groups[0]["L"], meta)
+        with open(os.path.join(args.out, "decompose.json"), "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res["summary"]), flush=True)
+        return
     meta["done"] = int(q["done"].sum())
     meta["stage"] = [int(x) for x in q["stage"]]
     meta["trials_per_walker"] = [int(x) for x in q["trials"]]

@@ -53,6 +53,12 @@ CONFIGS = {
     "p8pair": [dict(P8, n_windows=3, walkers_per_window=3), dict(P8, n_windows=1, walkers_per_window=1)],
     "p8sync": [dict(P8, n_windows=3, walkers_per_window=3),
                dict(P8, n_windows=3, walkers_per_window=3, stage_sync=1)],
+    # 16x16 in one plan: the measured REWL problem (8 windows, overlap 3/4, 4 walkers), the paper's
+    # own 16x16 shape (3 windows, overlap 1/2, 3 walkers; Sec. 3) and serial 2D-WL over the whole
+    # (E, M) space (Fig. 4(b)); all three share X = 10^4, so they run side by side at no extra cost
+    "c2p16": [dict(L=16, n_windows=8, overlap=(3, 4), walkers_per_window=4, k_final=20, interval=10_000),
+              dict(L=16, n_windows=3, overlap=(1, 2), walkers_per_window=3, k_final=20, interval=10_000),
+              dict(L=16, n_windows=1, overlap=(1, 2), walkers_per_window=1, k_final=20, interval=10_000)],
 }
 
 
@@ -67,7 +73,52 @@ def rel_diff(a, b):
     return 2.0 * np.abs(np.tanh(0.5 * (a - b)))
 
 
-def decompose(R, plan, probs, L, meta):
+def paper_pair(R, plan, probs, tags, L):
+    """Groups 1 (REWL) and 2 (serial 2D-WL) of each replica, evaluated where they are: the relative
+    error of the marginal against the exact g(E) (sum normalisation), and Eq. 5 between the two
+    joint DOS over the bins both visited (Sec. 3, Fig. 4(b) and Fig. 5(a))."""
+    N = L * L
+    ex = exact_lnge(L)
+    ok = np.isfinite(ex) & (ex > 0)
+    by = {}
+    for i, (gi, r) in enumerate(tags):
+        if gi in (1, 2):
+            by.setdefault(r, {})[gi] = i
+    rows = []
+    for r, d in sorted(by.items()):
+        out = {"replica": r}
+        joints = {}
+        for gi, i in d.items():
+            q = plan.query_windows(i)
+            j, g, em = plan.merge(i, "sum")
+            g = g.cpu().numpy()
+            eps = np.abs(g[ok] - ex[ok]) / ex[ok]
+            joints[gi] = j.cpu().numpy()
+            out[("rewl", "serial")[gi - 1]] = {
+                "stage": int(q["stage"].min()), "trials_per_walker": int(q["trials"][0]),
+                "max_eps": float(eps.max()), "mean_eps": float(eps.mean()),
+                "max_eps_inner": float(eps[1:-1].max()), "bins_visited": int(np.isfinite(joints[gi]).sum())}
+        a, b = joints[1], joints[2]
+        both = np.isfinite(a) & np.isfinite(b)
+        dd = rel_diff(a[both], b[both])
+        e_rows = np.nonzero(both)[0]
+        edge = (e_rows <= 2) | (e_rows >= N - 2)
+        out["eq5"] = {"bins": int(both.sum()), "only_one": int((np.isfinite(a) ^ np.isfinite(b)).sum()),
+                      "mean": float(dd.mean()), "median": float(np.median(dd)), "max": float(dd.max()),
+                      "mean_interior": float(dd[~edge].mean()), "mean_edges": float(dd[edge].mean())}
+        rows.append(out)
+    summ = {}
+    for key in ("rewl", "serial"):
+        for f in ("stage", "max_eps", "mean_eps", "max_eps_inner"):
+            v = np.array([row[key][f] for row in rows], dtype=float)
+            summ[f"{key}.{f}"] = [float(v.min()), float(np.median(v)), float(v.max())]
+    for f in ("mean", "median", "mean_interior", "mean_edges"):
+        v = np.array([row["eq5"][f] for row in rows])
+        summ[f"eq5.{f}"] = [float(v.min()), float(np.median(v)), float(v.max())]
+    return {"summary": summ, "per_replica": rows}
+
+
+def decompose(R, plan, probs, L, meta, index=None):
     """Piece and join parts of each replica's marginal error (see the module notes)."""
     from oracle import merge as MG
     N = L * L
@@ -75,7 +126,8 @@ def decompose(R, plan, probs, L, meta):
     ok = np.isfinite(ex) & (ex > 0)
     lse = MG._lse
     rows = []
-    for i, p in enumerate(probs):
+    index = list(range(len(probs))) if index is None else index
+    for i, p in zip(index, probs):
         pieces = []
         for w in range(p.n_windows):
             frags = [plan.walker(i, w, a)["lng"] for a in range(p.walkers_per_window)]
@@ -116,8 +168,10 @@ def decompose(R, plan, probs, L, meta):
             summ[f"{part}@E={4 * e - 2 * N}"] = {"mean": float(v.mean()), "se": float(v.std(ddof=1) / np.sqrt(v.size)),
                                                 "rms": float(np.sqrt((v ** 2).mean())), "n": int(v.size)}
     q = plan.query()
-    return {"replicas": len(probs), "stage_min_max": [int(q["stage"].min()), int(q["stage"].max())],
-            "trials_per_walker_min_max": [int(q["trials"].min()), int(q["trials"].max())],
+    st = q["stage"][index]
+    tr = q["trials"][index]
+    return {"replicas": len(probs), "stage_min_max": [int(st.min()), int(st.max())],
+            "trials_per_walker_min_max": [int(tr.min()), int(tr.max())],
             "seconds": meta["seconds"], "summary": summ,
             "max_eps_per_replica": [r["max_eps"] for r in rows],
             "max_eps_inner_per_replica": [r["max_eps_inner"] for r in rows], "per_replica": rows}
@@ -172,10 +226,15 @@ def main():
     meta["seconds"] += time.time() - t0
     q = plan.query()
     if args.decompose:
-        res = decompose(R, plan, probs, groups[0]["L"], meta)
+        g0 = [i for i, (gi, _) in enumerate(tags) if gi == 0]
+        res = decompose(R, plan, [probs[i] for i in g0], groups[0]["L"], meta, index=g0)
+        if len(groups) == 3:
+            res["paper_shape"] = paper_pair(R, plan, probs, tags, groups[0]["L"])
         with open(os.path.join(args.out, "decompose.json"), "w") as f:
             json.dump(res, f, indent=1)
         print(json.dumps(res["summary"]), flush=True)
+        if "paper_shape" in res:
+            print(json.dumps(res["paper_shape"]["summary"]), flush=True)
         return
     meta["done"] = int(q["done"].sum())
     meta["stage"] = [int(x) for x in q["stage"]]

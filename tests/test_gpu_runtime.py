@@ -71,3 +71,28 @@ def test_checkpoint_resume_is_bit_exact():
     other = R.Plan(_probs(R, 5, k_final=7, interval=500))
     with pytest.raises(R.RewlError):
         other.load(blob)
+
+
+@pytest.mark.parametrize("form", ["batched", "plain"])
+def test_int64_headroom_guard_reports_overflow(form):
+    """ln g is int64 in units of 2^-K and every visit at stage s adds 2^(K-s): with K = 40 a walker
+    that stays at stage 0 (100 % flatness is never reached) adds 2^40 per trial, and its ln g could
+    pass 2^62 after 2^22 trials.  The guard must report REWL_EOVERFLOW at the first boundary whose
+    interval would take the bound past 2^62 (interval 5 for 10^6 trials per interval), not before."""
+    R = _R()
+    X = 1_000_000
+    p = R.Problem(L=4, n_windows=1, walkers_per_window=1, k_final=40, flat=(1, 1), interval=X, seed=3)
+    tn = R.Tuning(form=R.FORM_PLAIN) if form == "plain" else R.Tuning(graph_intervals=1)
+    _say(f"case: int64 headroom guard, K = 40, {form} form")
+    plan = R.Plan([p], tn)
+    plan.init()
+    first_bad = next(k for k in range(1, 100) if k * X * 2 ** 40 > 2 ** 62)
+    assert first_bad == 5
+    for k in range(1, first_bad):
+        plan.run(1)
+        q = plan.query()
+        assert int(q["stage"][0]) == 0 and int(q["trials"][0]) == k * X
+    plan.run(1)
+    with pytest.raises(R.RewlError) as ei:
+        plan.query()
+    assert ei.value.status == R.REWL_EOVERFLOW

@@ -96,3 +96,22 @@ def test_int64_headroom_guard_reports_overflow(form):
     with pytest.raises(R.RewlError) as ei:
         plan.query()
     assert ei.value.status == R.REWL_EOVERFLOW
+
+
+def test_destroyed_plan_leaves_no_kernel_writing_freed_memory():
+    """rewl_plan_destroy (Plan.close / del) waits for the plan's stream: after a long enqueued run
+    and an immediate delete, a tensor that the caching allocator hands the same memory must keep
+    what is written into it."""
+    import torch
+    R = _R()
+    probs = _probs(R, 64, interval=200_000)
+    plan = R.Plan(probs, R.Tuning(graph_intervals=4))
+    plan.init()
+    sizes = list(plan.sizes)
+    plan.run(8)                      # about a second of enqueued work on the plan's stream
+    del plan                         # returns the buffers to the caching allocator
+    for n in sizes:
+        x = torch.empty(max(1, n), dtype=torch.uint8, device="cuda")
+        x.fill_(0x5A)
+        torch.cuda.synchronize()
+        assert bool((x == 0x5A).all())

@@ -37,16 +37,17 @@ C4 = dict(L=64, n_windows=64, overlap=(3, 4), walkers_per_window=4, k_final=20, 
 # A mixed batch of lattice sizes with uneven window counts, run in the same
 # launches as the 32x32 problems.
 MIXED = [dict(C3, L=L, n_windows=nw) for L, nw in ((8, 2), (12, 4), (16, 8), (24, 12), (32, 16))]
-# (table layout, walkers per workgroup, grid waves per CU, walkers per wavefront) used for the
-# extra workloads measured next to the headline (the autotuner's choices on MI355X)
-EXTRA_TUNING = {"c2": (0, 256, 4, 0), "c3mix": (0, 64, 8, 0)}
+# table layout of the extra workloads measured next to the headline (their launch shape is
+# autotuned on the plan itself); their default replica counts fill the 1024 SIMDs with one
+# wavefront of 64 walkers each (c2: two tiles of walkers per wavefront)
+EXTRA_LAYOUT = {"c2": 0, "c3mix": 0}
 # name -> (problems of one replica, default replica count, description)
 WORKLOADS = {
     "c2": ([C2], 4096, "16x16 periodic Ising 2D-REWL (8 windows x 4 walkers, overlap 3/4, ln f 1 -> 2^-20, "
                        "80% flat, exchange every 10^4 trials)"),
-    "c3": ([C3], 240, "32x32 periodic Ising 2D-REWL (16 windows x 8 walkers, overlap 3/4, ln f 1 -> 2^-24, "
+    "c3": ([C3], 512, "32x32 periodic Ising 2D-REWL (16 windows x 8 walkers, overlap 3/4, ln f 1 -> 2^-24, "
                       "80% flat, exchange every 10^4 trials)"),
-    "c3mix": ([C3] + MIXED, 100, "32x32 periodic Ising 2D-REWL (16 windows x 8 walkers, overlap 3/4, ln f 1 -> "
+    "c3mix": ([C3] + MIXED, 141, "32x32 periodic Ising 2D-REWL (16 windows x 8 walkers, overlap 3/4, ln f 1 -> "
                                  "2^-24, 80% flat, exchange every 10^4 trials) plus a mixed batch of L in "
                                  "{8,12,16,24,32} with 2/4/8/12/16 windows x 8 walkers, all in the same launches"),
     "c4": ([C4], 0, "64x64 periodic Ising 2D-REWL (64 windows x 4 walkers, overlap 3/4, ln f 1 -> 2^-20, "
@@ -54,14 +55,25 @@ WORKLOADS = {
 }
 # replicas 0 = as many as fit in the device memory (leaving MEM_SPARE bytes)
 MEM_SPARE = 12 << 30
-# Serial 2D-WL on the 4x4 lattice (one window, one walker), run to its last stage.
-C1 = dict(L=4, n_windows=1, overlap=(3, 4), walkers_per_window=1, k_final=16, flat=(4, 5), interval=10_000)
 
 
-def full_run(R, torch, replicas):
-    """Whole runs to the final ln f (Sec. 2): the 4x4 serial 2D-WL problem once in the plain form,
-    once in the batched form (same final state), and `replicas` independent copies in one batched
-    plan; trials per second from the first sweep to the boundary where the last problem ends."""
+# Whole runs to the end (--full-run): the 4x4 serial 2D-WL problem, or the 8x8 REWL problem of the
+# paper's experiments (3 windows with overlap 1/2 x 3 walkers, ln f 1 -> 2^-20).
+FULL_RUN = {
+    "c1": (dict(L=4, n_windows=1, overlap=(3, 4), walkers_per_window=1, k_final=16, flat=(4, 5), interval=10_000),
+           "4x4 periodic Ising serial 2D-WL (1 window x 1 walker, ln f 1 -> 2^-16, 80% flat, flatness check every "
+           "10^4 trials), run to the end"),
+    "p8": (dict(L=8, n_windows=3, overlap=(1, 2), walkers_per_window=3, k_final=20, flat=(4, 5), interval=10_000),
+           "8x8 periodic Ising 2D-REWL (3 windows x 3 walkers, overlap 1/2, ln f 1 -> 2^-20, 80% flat, exchange "
+           "every 10^4 trials), run to the end"),
+}
+
+
+def full_run(R, torch, replicas, which="c1"):
+    """Whole runs to the final ln f (Sec. 2): one problem once in the plain form, once in the batched
+    form (same final state, so the same final ln f), and `replicas` independent copies in one
+    batched plan; trials per second from the first sweep to the boundary where the last problem
+    ends."""
     def to_end(plan, chunk):
         plan.stream.synchronize()
         torch.cuda.synchronize()
@@ -74,24 +86,29 @@ def full_run(R, torch, replicas):
             if q["done"].all():
                 break
         return time.perf_counter() - t0, n, q
-    out = {"workload": "4x4 periodic Ising serial 2D-WL (1 window x 1 walker, ln f 1 -> 2^-16, 80% flat, "
-                       "flatness check every 10^4 trials), run to the end"}
-    one = problems(1, R, C1)
+    cfg, text = FULL_RUN[which]
+    out = {"workload": text}
+    one = problems(1, R, cfg)
     pp = R.Plan(one, R.Tuning(form=R.FORM_PLAIN))
     pp.init()
     Tp, _, qp = to_end(pp, 16)
     pb = R.Plan(one, R.Tuning(graph_intervals=16))
     pb.init()
     Tb, _, qb = to_end(pb, 16)
-    same = bool((pp.walker(0, 0, 0)["lng"] == pb.walker(0, 0, 0)["lng"]).all())
-    trials1 = int(qp["trials"][0])
+    same = all(bool((pp.walker(0, w, a)["lng"] == pb.walker(0, w, a)["lng"]).all())
+               for w in range(cfg["n_windows"]) for a in range(cfg["walkers_per_window"]))
+    n1 = cfg["n_windows"] * cfg["walkers_per_window"]
+    trials1 = int(qp["trials"][0]) * n1
     out.update({"one_problem_trials": trials1, "plain_s": Tp, "batched_s": Tb, "plain_value": trials1 / Tp,
-                "batched_value": trials1 / Tb, "identical_final_state": same})
+                "batched_value": trials1 / Tb, "speedup": Tp / Tb, "identical_final_state": same,
+                "final_stage": int(qp["stage"][0])})
+    pp.close()
+    pb.close()
     del pp, pb
-    plan = R.Plan(problems(replicas, R, C1), R.Tuning(graph_intervals=16))
+    plan = R.Plan(problems(replicas, R, cfg), R.Tuning(graph_intervals=16))
     plan.init()
     T, n, q = to_end(plan, 256)
-    total = int(q["trials"].sum())
+    total = int(q["trials"].sum()) * n1
     out.update({"replicas": replicas, "batch_s": T, "batch_intervals": n, "batch_trials": total,
                 "batch_value": total / T, "unit": "spin-flip attempts/s",
                 "trials_per_problem_min_max": [int(q["trials"].min()), int(q["trials"].max())]})
@@ -207,7 +224,9 @@ def main():
     ap.add_argument("--wg", type=int, default=0, help="walkers per workgroup (0 = library's choice)")
     ap.add_argument("--grid-waves", type=int, default=0, help="persistent grid waves per CU (0 = library's choice)")
     ap.add_argument("--full-run", type=int, default=0, metavar="R",
-                    help="only run the 4x4 serial problem to its end: plain, batched, and R replicas batched")
+                    help="only run one problem to its end: plain, batched, and R replicas batched")
+    ap.add_argument("--full-run-problem", default="c1", choices=sorted(FULL_RUN),
+                    help="c1: the 4x4 serial problem; p8: the 8x8 REWL problem (3 x 3 walkers)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -231,7 +250,7 @@ def main():
     import paper_1508_02748_amd as R
 
     if args.full_run:
-        print(json.dumps(full_run(R, torch, args.full_run)), flush=True)
+        print(json.dumps(full_run(R, torch, args.full_run, args.full_run_problem)), flush=True)
         return
 
     dev = "cuda:0"
@@ -335,11 +354,12 @@ def main():
     extras = {}
     for name in ([] if args.no_extras else [n for n in ("c2", "c3mix") if n != args.workload]):
         eunit, er, etext = WORKLOADS[name]
-        lay, wg, gw, wpw_e = EXTRA_TUNING[name]
-        ep = R.Plan(problems(er, R, eunit), R.Tuning(graph_intervals=K, walkers_per_wg=wg, grid_waves_per_cu=gw,
-                                                     walkers_per_wave=wpw_e, table_layout=lay, profile=1),
-                    device=dev)
+        lay = EXTRA_LAYOUT[name]
+        ep = R.Plan(problems(er, R, eunit), R.Tuning(graph_intervals=K, table_layout=lay), device=dev)
         ep.init()
+        eb = autotune(ep, intervals=1, use_cache=False, graph_lengths=(K,))
+        wg, gw, wpw_e = eb.walkers_per_wg, eb.grid_waves_per_cu, eb.walkers_per_wave
+        ep.set_profile(True)
         eX = eunit[0]["interval"]
         Te = time_plan(er, ep, args.extra_steps, 3)
         ems = float(np.mean(ep.sweep_times()))

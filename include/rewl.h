@@ -53,7 +53,8 @@ typedef enum {
     REWL_ENOMEM = -2,     /* host allocation failed */
     REWL_EDEVICE = -3,    /* a HIP call or kernel failed */
     REWL_ESTATE = -4,     /* plan not bound / in error / entry walk exceeded its cap */
-    REWL_EOVERFLOW = -5,  /* ln g would leave int64 headroom */
+    REWL_EOVERFLOW = -5,  /* ln g would leave int64 headroom, or a bin has 2^31
+                             visits in one stage (its 32-bit count could wrap) */
     REWL_ENOTREADY = -6   /* reserved */
 } rewl_status;
 
@@ -69,7 +70,7 @@ typedef struct {
     int32_t flat_num;            /* flat iff min H >= num/den * mean H over */
     int32_t flat_den;            /*   visited bins; 4/5 = the paper's 80 % */
     int64_t interval;            /* trials per walker between flatness checks and
-                                    exchange rounds; >= 1 */
+                                    exchange rounds; 1 .. 2^30 */
     uint64_t seed;               /* Philox key */
     int32_t init;                /* 0: spins Bernoulli(1/2) from Philox; 1: all +1 */
     int32_t stage_sync;          /* REWL_SYNC_PROBLEM (the paper) or REWL_SYNC_WINDOW */
@@ -137,7 +138,13 @@ typedef struct {
                                  a small batch over more CUs; 0 = 64 */
     int32_t table_layout;     /* REWL_LAYOUT_DENSE or REWL_LAYOUT_BAND (below); fixed when
                                  the plan is created */
-    int32_t reserved;         /* must be 0 */
+    int32_t audit_shift;      /* the 32-bit stage visit counts are audited once per
+                                 2^audit_shift stage trials of a walker; 0 = 30, else
+                                 1..30; every interval must be at most 2^audit_shift.
+                                 An audit stops the run (REWL_EOVERFLOW) once a bin has
+                                 2^(audit_shift + 1) visits in one stage, so a small
+                                 value only tests that guard.  Fixed when the plan is
+                                 created. */
 } rewl_tuning;
 
 /* How each walker's tables are stored (rewl_tuning.table_layout).  Both
@@ -155,8 +162,10 @@ enum { REWL_LAYOUT_DENSE = 0, REWL_LAYOUT_BAND = 1 };
 
 /* Buffers the caller provides (device memory). */
 enum {
-    REWL_BUF_TABLES = 0,  /* ln g (8 B per bin) and its stage snapshot (4 B per bin) of
-                             each walker's window table (4 x 4 tiles of (e, m)) */
+    REWL_BUF_TABLES = 0,  /* ln g (int64, 8 B per bin) of each walker's window table
+                             (4 x 4 tiles of (e, m)), then the stage base (uint32,
+                             4 B per bin, same bin order): the stage's visit count
+                             is H = (ln g >> (K - s)) - base mod 2^32; 12 B per bin */
     REWL_BUF_SPINS = 1,   /* bit-packed configurations */
     REWL_BUF_STATE = 2,   /* descriptors, walker and problem state, scratch */
     REWL_NBUF = 3
@@ -205,8 +214,10 @@ rewl_status rewl_init(rewl_plan* plan);
 rewl_status rewl_run(rewl_plan* plan, int64_t n_intervals);
 
 /* The three parts of an interval, separately: n trials per walker of every
- * unfinished problem; the flatness check and stage advance ("reduce ln f");
- * the exchange round of the boundary last closed by rewl_reduce_lnf. */
+ * unfinished problem (enqueued in pieces of at most 2^30 trials, each followed
+ * by the audit of the 32-bit stage visit counts); the flatness check and
+ * stage advance ("reduce ln f"); the exchange round of the boundary last
+ * closed by rewl_reduce_lnf. */
 rewl_status rewl_sweep(rewl_plan* plan, int64_t n_trials);
 rewl_status rewl_reduce_lnf(rewl_plan* plan);
 rewl_status rewl_exchange(rewl_plan* plan);

@@ -48,7 +48,7 @@ class _Problem(C.Structure):
 class _Tuning(C.Structure):
     _fields_ = [("form", C.c_int32), ("walkers_per_wg", C.c_int32), ("graph_intervals", C.c_int32),
                 ("grid_waves_per_cu", C.c_int32), ("profile", C.c_int32), ("walkers_per_wave", C.c_int32),
-                ("table_layout", C.c_int32), ("reserved", C.c_int32)]
+                ("table_layout", C.c_int32), ("audit_shift", C.c_int32)]
 
 
 _lib = None
@@ -164,10 +164,11 @@ class Tuning:
     profile: int = 0
     walkers_per_wave: int = 0
     table_layout: int = LAYOUT_DENSE
+    audit_shift: int = 0
 
     def _c(self):
         return _Tuning(self.form, self.walkers_per_wg, self.graph_intervals, self.grid_waves_per_cu,
-                       self.profile, self.walkers_per_wave, self.table_layout, 0)
+                       self.profile, self.walkers_per_wave, self.table_layout, self.audit_shift)
 
 
 def plan_bytes(problems, table_layout=LAYOUT_DENSE):

@@ -141,7 +141,7 @@ struct rewl_plan {
     size_t sizes[REWL_NBUF] = {0, 0, 0};
     // STATE buffer offsets
     size_t off_wd = 0, off_pd = 0, off_pairs = 0, off_e = 0, off_m = 0, off_t = 0, off_te = 0,
-           off_nseen = 0, off_flag = 0, off_scan = 0, off_stage = 0, off_wdone = 0, off_tstage = 0, off_adv = 0,
+           off_nseen = 0, off_flag = 0, off_scan = 0, off_aud = 0, off_stage = 0, off_wdone = 0, off_tstage = 0, off_adv = 0,
            off_lngb = 0, off_tseen = 0, off_done = 0, off_rnd = 0, off_xr = 0, off_xon = 0, off_cnt = 0;
     int32_t n_win = 0;  // windows over all problems
     int split = 0;      // the split of every problem of the plan (energy 0, magnetization 1, both 2)
@@ -192,7 +192,7 @@ rewl_status validate(const rewl_problem& q, int idx) {
     if (q.walkers_per_window < 1 || q.walkers_per_window > 256) return bad("walkers_per_window must be 1..256");
     if (q.k_final < 0 || q.k_final > 40) return bad("k_final must be 0..40");
     if (q.flat_den < 1 || q.flat_num < 0 || q.flat_num > q.flat_den) return bad("flatness must be num/den <= 1");
-    if (q.interval < 1) return bad("interval must be >= 1");
+    if (q.interval < 1 || q.interval > (1ll << H_AUDIT_SHIFT)) return bad("interval must be 1..2^30");
     if (q.init != 0 && q.init != 1) return bad("init must be 0 or 1");
     if (q.stage_sync != REWL_SYNC_PROBLEM && q.stage_sync != REWL_SYNC_WINDOW)
         return bad("stage_sync must be REWL_SYNC_PROBLEM or REWL_SYNC_WINDOW");
@@ -231,7 +231,7 @@ rewl_status validate_tuning(const rewl_tuning& tn) {
     if (tn.profile && tn.form != REWL_FORM_BATCHED) return fail(REWL_EINVAL, "profiling times the batched form");
     if (tn.table_layout != REWL_LAYOUT_DENSE && tn.table_layout != REWL_LAYOUT_BAND)
         return fail(REWL_EINVAL, "table_layout must be REWL_LAYOUT_DENSE or REWL_LAYOUT_BAND");
-    if (tn.reserved != 0) return fail(REWL_EINVAL, "tuning.reserved must be 0");
+    if (tn.audit_shift < 0 || tn.audit_shift > H_AUDIT_SHIFT) return fail(REWL_EINVAL, "audit_shift 0..30");
     return REWL_OK;
 }
 
@@ -242,7 +242,7 @@ DevState make_state(rewl_plan* P) {
     S.pd = reinterpret_cast<const PDesc*>(st + P->off_pd);
     S.pairs = reinterpret_cast<const PairDesc*>(st + P->off_pairs);
     S.lng = static_cast<int64_t*>(P->buf[REWL_BUF_TABLES]);
-    S.snap = S.lng + P->n_bins;
+    S.hb = reinterpret_cast<uint32_t*>(S.lng + P->n_bins);
     S.spins = static_cast<uint32_t*>(P->buf[REWL_BUF_SPINS]);
     S.e = reinterpret_cast<int32_t*>(st + P->off_e);
     S.m = reinterpret_cast<int32_t*>(st + P->off_m);
@@ -251,6 +251,7 @@ DevState make_state(rewl_plan* P) {
     S.nseen = reinterpret_cast<uint32_t*>(st + P->off_nseen);
     S.flag = reinterpret_cast<uint32_t*>(st + P->off_flag);
     S.scan = reinterpret_cast<uint32_t*>(st + P->off_scan);
+    S.aud = reinterpret_cast<uint32_t*>(st + P->off_aud);
     S.stage = reinterpret_cast<int32_t*>(st + P->off_stage);
     S.wdone = reinterpret_cast<int32_t*>(st + P->off_wdone);
     S.tstage = reinterpret_cast<int64_t*>(st + P->off_tstage);
@@ -266,6 +267,7 @@ DevState make_state(rewl_plan* P) {
     S.n_prob = static_cast<int32_t>(P->pd.size());
     S.n_pairs = static_cast<int32_t>(P->pairs.size());
     S.n_win = P->n_win;
+    S.audit_shift = P->tune.audit_shift > 0 ? P->tune.audit_shift : H_AUDIT_SHIFT;
     return S;
 }
 
@@ -508,6 +510,8 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
     for (int i = 1; i < n_problems; ++i)
         if (problems[i].split != problems[0].split)
             return fail(REWL_EINVAL, "all problems of a plan must share the split");
+    if (tn.audit_shift > 0 && X > (1ll << tn.audit_shift))
+        return fail(REWL_EINVAL, "the interval exceeds 2^audit_shift trials");
 
     if (tn.table_layout == REWL_LAYOUT_BAND && problems[0].split == REWL_SPLIT_BOTH)
         return fail(REWL_EINVAL, "the band layout applies to one-coordinate splits");
@@ -622,6 +626,7 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
     P->off_nseen = take(nw * 4);
     P->off_flag = take(nw * 4);
     P->off_scan = take(nw * 4);
+    P->off_aud = take(nw * 4);
     const size_t nwn = static_cast<size_t>(P->n_win);
     P->off_stage = take(nwn * 4);
     P->off_wdone = take(nwn * 4);
@@ -634,7 +639,7 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
     P->off_xr = take(np * 8);
     P->off_xon = take(np * 4);
     P->off_cnt = take(16);
-    P->sizes[REWL_BUF_TABLES] = align_up(2 * bins * sizeof(int64_t), A);
+    P->sizes[REWL_BUF_TABLES] = align_up(bins * (sizeof(int64_t) + sizeof(uint32_t)), A);
     P->sizes[REWL_BUF_SPINS] = align_up(words * 4, A);
     P->sizes[REWL_BUF_STATE] = o;
     *out = P;
@@ -764,16 +769,23 @@ rewl_status rewl_sweep(rewl_plan* P, int64_t n) {
     if (s != REWL_OK) return s;
     if (!P->initialised) return fail(REWL_ESTATE, "rewl_init has not run");
     if (n < 0) return fail(REWL_EINVAL, "negative trial count");
-    if (P->tune.form == REWL_FORM_PLAIN) {
-        const int wg = wg_of(P);
-        for (const PDesc& q : P->pd)
-            for (int w = 0; w < q.nwin; ++w)
-                HIPCHK(P, launch_sweep(P->S, q.walker_off + static_cast<int64_t>(w) * q.W, q.W, n, q.L, wg, 0,
-                                       P->tune.walkers_per_wave, P->split, P->layout, P->stream),
-                       "plain sweep launch");
-        return REWL_OK;
+    // pieces of at most 2^30 trials, each followed by the stage-count audit
+    for (int64_t done = 0; done < n;) {
+        const int64_t m = std::min<int64_t>(n - done, 1ll << P->S.audit_shift);
+        if (P->tune.form == REWL_FORM_PLAIN) {
+            const int wg = wg_of(P);
+            for (const PDesc& q : P->pd)
+                for (int w = 0; w < q.nwin; ++w)
+                    HIPCHK(P, launch_sweep(P->S, q.walker_off + static_cast<int64_t>(w) * q.W, q.W, m, q.L, wg, 0,
+                                           P->tune.walkers_per_wave, P->split, P->layout, P->stream),
+                           "plain sweep launch");
+        } else if ((s = enqueue_sweep(P, m)) != REWL_OK) {
+            return s;
+        }
+        HIPCHK(P, launch_flat(P->S, P->stream, 1), "audit launch");
+        done += m;
     }
-    return enqueue_sweep(P, n);
+    return REWL_OK;
 }
 
 rewl_status rewl_reduce_lnf(rewl_plan* P) {
@@ -844,6 +856,8 @@ rewl_status rewl_query(rewl_plan* P, int32_t* stage_out, int32_t* done_out, int6
         if (trials_out) trials_out[p] = t[P->pd[p].walker_off];
     }
     if (cnt[1] & ERR_OVERFLOW) return fail(REWL_EOVERFLOW, "ln g would exceed 2^62 units");
+    if (cnt[1] & ERR_HWRAP)
+        return fail(REWL_EOVERFLOW, "a bin has 2^31 visits in one stage: the 32-bit stage count would wrap");
     if (cnt[1] & ERR_LAYOUT) return fail(REWL_ESTATE, "an exchanged state lies outside a stored table band");
     return REWL_OK;
 }
@@ -883,7 +897,8 @@ rewl_status rewl_read_walker(rewl_plan* P, int32_t prob, int32_t w, int32_t a, i
     const int nM = R.mhi - R.mlo + 1;  // columns
     const size_t nb = static_cast<size_t>(nE) * nM;
     if ((lng || H) && cap_bins < nb) return fail(REWL_EINVAL, "cap_bins too small");
-    std::vector<int64_t> tl, ts;
+    std::vector<int64_t> tl;
+    std::vector<uint32_t> ts;
     std::vector<uint32_t> words;
     std::vector<int32_t> ev, mv, stage;
     std::vector<int64_t> tv;
@@ -892,7 +907,7 @@ rewl_status rewl_read_walker(rewl_plan* P, int32_t prob, int32_t w, int32_t a, i
         ts.resize(d.nbins);
         HIPCHK(P, hipMemcpyAsync(tl.data(), P->S.lng + d.table_off, d.nbins * sizeof(int64_t),
                                  hipMemcpyDeviceToHost, P->stream), "table read");
-        HIPCHK(P, hipMemcpyAsync(ts.data(), P->S.snap + d.table_off, d.nbins * sizeof(int64_t),
+        HIPCHK(P, hipMemcpyAsync(ts.data(), P->S.hb + d.table_off, d.nbins * sizeof(uint32_t),
                                  hipMemcpyDeviceToHost, P->stream), "table read");
     }
     const size_t nwords = static_cast<size_t>(q.L) * q.row_words;
@@ -912,7 +927,8 @@ rewl_status rewl_read_walker(rewl_plan* P, int32_t prob, int32_t w, int32_t a, i
                 const int64_t ti = table_index_or_none(d, R.elo + er, R.mlo + mm);
                 const size_t oi = static_cast<size_t>(er) * nM + mm;
                 if (lng) lng[oi] = ti < 0 ? 0 : tl[ti];
-                if (H) H[oi] = ti < 0 ? 0 : static_cast<uint64_t>(tl[ti] - ts[ti]) >> sh;
+                if (H)
+                    H[oi] = ti < 0 ? 0 : static_cast<uint32_t>(static_cast<uint32_t>(static_cast<uint64_t>(tl[ti]) >> sh) - ts[ti]);
             }
     if (spins)
         for (int r = 0; r < q.L; ++r)
@@ -1281,6 +1297,8 @@ extern "C" rewl_status rewl_set_tuning(rewl_plan* P, const rewl_tuning* tuning) 
     rewl_status s = validate_tuning(*tuning);
     if (s != REWL_OK) return s;
     if (tuning->form != P->tune.form) return fail(REWL_EINVAL, "the form of a plan cannot change");
+    if (tuning->table_layout != P->tune.table_layout) return fail(REWL_EINVAL, "the table layout of a plan cannot change");
+    if (tuning->audit_shift != P->tune.audit_shift) return fail(REWL_EINVAL, "the audit shift of a plan cannot change");
     P->tune = *tuning;
     P->profile = tuning->profile != 0;
     if (P->graph) {
@@ -1292,7 +1310,7 @@ extern "C" rewl_status rewl_set_tuning(rewl_plan* P, const rewl_tuning* tuning) 
 }
 
 namespace {
-constexpr uint64_t SAVE_MAGIC = 0x3330574C57455232ull;  // "2REWLW03": problems carry the split
+constexpr uint64_t SAVE_MAGIC = 0x3430574C57455232ull;  // "2REWLW04": 32-bit stage base, audit epochs
 struct SaveHeader {
     uint64_t magic;
     uint64_t n_problems;

@@ -6,20 +6,28 @@
 
 namespace rewl {
 
-// Window tables.  Each walker owns two int64 tables over its window's
-// rectangle of (e, m) bins: rows e in [lo, hi] and all m in [0, N] when the
-// windows split the energy, all rows e and columns m in [lo, hi] when they split
-// the magnetization, both ranges for windows in both coordinates.  The table
-// row is e - e0, the column m - m0 (e0, m0 the rectangle's corner).  They hold
-// ln g in units of 2^-K (> 0 marks a bin the walker has visited; ln g only
-// grows), and a snapshot of ln g taken when the current stage began.  Every
-// visit in stage s adds 2^(K-s), so the visit count of the stage is H = (ln g -
-// snapshot) >> (K - s): a trial touches only ln g, and resetting H at a stage
-// change is one copy of the table.
+// Window tables.  Each walker owns two tables over its window's rectangle of
+// (e, m) bins: rows e in [lo, hi] and all m in [0, N] when the windows split
+// the energy, all rows e and columns m in [lo, hi] when they split the
+// magnetization, both ranges for windows in both coordinates.  The table row is
+// e - e0, the column m - m0 (e0, m0 the rectangle's corner).  The first holds
+// ln g as int64 in units of 2^-K (> 0 marks a bin the walker has visited; ln g
+// only grows).  The second, the stage base, holds uint32 (ln g >> (K - s))
+// modulo 2^32 as it was when the current stage s began.  Every visit in stage
+// s adds 2^(K-s), and ln g keeps its residue modulo 2^(K-s) through the stage,
+// so the stage's visit count is H = (ln g >> (K - s)) - base, exact modulo
+// 2^32: a trial touches only ln g, and resetting H at a stage change is one
+// pass over the table.  H < 2^32 is guarded by an audit (k_flat): at the first
+// check after a walker's stage trial count passes a multiple of 2^a (a =
+// audit_shift <= 30) every bin must show H < 2^(a+1), else the run stops with
+// an overflow error.  Checks come at least every 2^a trials (the interval X <=
+// 2^a, and rewl_sweep pieces), so two audits lie less than 2^(a+1) trials
+// apart, no bin exceeds 2^(a+1) + 2^(a+1) <= 2^32 visits between them, and no
+// count can wrap unnoticed.
 //
 // Both tables are stored in tiles of 4 energy rows x 4 magnetization columns
-// (16 bins = 128 bytes, one cache line), tiles row-major: a walker's trial
-// bins (e-2..e+2, m-1 / m+1) fall into about two lines instead of five.
+// (16 bins; 128 bytes of ln g, one cache line), tiles row-major: a walker's
+// trial bins (e-2..e+2, m-1 / m+1) fall into about two lines instead of five.
 //
 // Band layout (energy windows): a state in energy bin e has at least e/2
 // minority spins (each unsatisfied bond touches a minority spin, which has four
@@ -43,8 +51,8 @@ __host__ __device__ inline int band_c0(int e0, int tr) { return ((e0 + 4 * tr + 
 
 // Static description of one walker.
 struct WDesc {
-    uint64_t table_off;  // first bin of its tiled table (ln g; the snapshot sits at the same
-                         // offset of the snapshot table)
+    uint64_t table_off;  // first bin of its tiled table (ln g; the stage base sits at the same
+                         // offset of the stage-base table)
     uint32_t spin_off;   // first word of its L x row_words packed spins
     int32_t prob;        // problem index
     int32_t lo, hi;      // window in the split coordinate (e, or m for the magnetization
@@ -109,7 +117,7 @@ struct DevState {
     const PDesc* pd;
     const PairDesc* pairs;
     int64_t* lng;     // ln g tables
-    int64_t* snap;    // ln g at the start of the current stage
+    uint32_t* hb;     // stage base: (ln g >> (K - s)) mod 2^32 at the start of stage s
     uint32_t* spins;
     // per walker
     int32_t* e;
@@ -119,6 +127,7 @@ struct DevState {
     uint32_t* nseen;  // bins with ln g > 0
     uint32_t* flag;   // flat in the current stage (latched)
     uint32_t* scan;   // chunk where the last flatness scan failed (a hint)
+    uint32_t* aud;    // (stage trials) >> audit_shift when its table was last audited
     // per window (index gwin)
     int32_t* stage;   // ln f = 2^-stage
     int32_t* wdone;   // the window has finished its last stage; its walkers stop
@@ -137,9 +146,14 @@ struct DevState {
     int32_t n_prob;
     int32_t n_pairs;
     int32_t n_win;      // windows over all problems
+    int32_t audit_shift;  // stage-count audit period 2^audit_shift trials (<= H_AUDIT_SHIFT)
 };
 
-enum : int32_t { ERR_OVERFLOW = 1, ERR_LAYOUT = 2 };
+enum : int32_t { ERR_OVERFLOW = 1, ERR_LAYOUT = 2, ERR_HWRAP = 4 };
+
+// Longest audit period of the 32-bit stage visit counts, log2 of trials (see
+// the table notes); a plan may audit more often (DevState::audit_shift).
+constexpr int H_AUDIT_SHIFT = 30;
 
 // Workspace of the merge of one problem.  The windows are joined in two
 // steps: first along E within each magnetization column (the windows sharing
@@ -189,7 +203,7 @@ hipError_t launch_entry(const DevState& S, int64_t cap, hipStream_t st);
 hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int64_t n_trials,
                         int l_max, int wg, int max_grid, int wpw, int split, int layout, hipStream_t st);
 hipError_t sweep_setup();
-hipError_t launch_flat(const DevState& S, hipStream_t st);
+hipError_t launch_flat(const DevState& S, hipStream_t st, int audit_only = 0);
 hipError_t launch_stage(const DevState& S, hipStream_t st);
 hipError_t launch_average(const DevState& S, hipStream_t st);
 hipError_t launch_snapshot(const DevState& S, hipStream_t st);

@@ -12,8 +12,9 @@
 //   * ln g: one int64 table per walker (single owner, no atomics) over the
 //     window rows e in [lo, hi] and all m in [0, N], in 4 x 4 tiles of
 //     (e, m) bins, one 128-byte line per tile, so the bins a walker can reach
-//     in the next few trials share a few lines.  H is not stored: a snapshot
-//     of ln g taken when the stage began gives H = (ln g - snapshot) >> (K - s).
+//     in the next few trials share a few lines.  H is not stored: a 32-bit
+//     stage base, (ln g >> (K - s)) taken when the stage began, gives
+//     H = (ln g >> (K - s)) - base.
 //     The walker keeps the bin it occupies in registers and writes it back only
 //     when it leaves, so a trial costs one 8-byte gather of the proposed bin
 //     plus, on acceptance, one 8-byte store.
@@ -166,6 +167,7 @@ __global__ void k_init(DevState S) {
     S.nseen[g] = 0;
     S.flag[g] = 0;
     S.scan[g] = 0;
+    S.aud[g] = 0;
     if (d.gid % P.W == 0) {  // first walker of its window
         const int wi = d.gwin;
         S.stage[wi] = 0;
@@ -464,33 +466,54 @@ __global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int6
 // One wavefront per walker scans its table in chunks of 64 bins, four chunks
 // (eight loads per lane) in flight at a time, starting where the previous
 // scan failed: the walker is flat iff every visited bin (ln g > 0) has
-// flat_den * H * n_seen >= flat_num * sum H, with H = (ln g - snapshot) >>
-// (K - s) and sum H = trials made in this stage.  The first failing chunk in
-// scan order ends the scan and is where the next one starts; the latch is
-// set only after a full pass, so the result does not depend on the order.
+// flat_den * H * n_seen >= flat_num * sum H, with H = (ln g >> (K - s)) -
+// base (mod 2^32) and sum H = trials made in this stage.  The first failing
+// chunk in scan order ends the scan and is where the next one starts; the
+// latch is set only after a full pass, so the result does not depend on the
+// order.
+//
+// Before that, once per 2^a stage trials (a = audit_shift), the whole table is
+// audited: every bin must have H < 2^(a+1) (see the table notes in
+// rewl_internal.h); flat and
+// unflat walkers alike, since a latched walker keeps walking.  audit_only
+// stops after the audit (after trials made outside an interval).
 constexpr int FLAT_GROUP = 4;
 
-__global__ void __launch_bounds__(256) k_flat(DevState S) {
+__device__ __forceinline__ uint32_t stage_visits(int64_t lng, uint32_t base, int sh) {
+    return static_cast<uint32_t>(static_cast<uint64_t>(lng) >> sh) - base;
+}
+
+__global__ void __launch_bounds__(256) k_flat(DevState S, int audit_only) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t g = static_cast<int64_t>(blockIdx.x) * 4 + wave;
     if (g >= S.n_walk) return;
     const WDesc d = S.wd[g];
     const int p = d.prob;
-    if (S.wdone[d.gwin] || S.flag[g]) return;
+    if (S.wdone[d.gwin]) return;
     const PDesc P = S.pd[p];
     const int sh = P.K - S.stage[d.gwin];
-    const uint64_t n = S.nseen[g];
     const uint64_t sum = static_cast<uint64_t>(S.t[g] - S.tstage[d.gwin]);
-    if (n == 0) return;
     const int64_t* tab = S.lng + d.table_off;
-    const int64_t* snp = S.snap + d.table_off;
+    const uint32_t* hb = S.hb + d.table_off;
     const int64_t nb = d.nbins;
+    const uint32_t epoch = static_cast<uint32_t>(sum >> S.audit_shift);
+    if (epoch != S.aud[g]) {
+        const uint32_t lim = 1u << (S.audit_shift + 1);
+        bool wrap = false;
+        for (int64_t i = lane; i < nb; i += 64) wrap = wrap || stage_visits(tab[i], hb[i], sh) >= lim;
+        if (__any(wrap) && lane == 0) atomicOr(&S.counters[1], ERR_HWRAP);
+        if (lane == 0) S.aud[g] = epoch;
+    }
+    if (audit_only || S.flag[g]) return;
+    const uint64_t n = S.nseen[g];
+    if (n == 0) return;
     const int64_t nch = (nb + 63) / 64;
     int64_t c0 = S.scan[g];
     if (c0 >= nch) c0 = 0;
     const unsigned __int128 rhs = static_cast<unsigned __int128>(static_cast<uint64_t>(P.flat_num)) * sum;
     for (int64_t k = 0; k < nch; k += FLAT_GROUP) {
-        int64_t c[FLAT_GROUP], l[FLAT_GROUP], sn[FLAT_GROUP];
+        int64_t c[FLAT_GROUP], l[FLAT_GROUP];
+        uint32_t b[FLAT_GROUP];
         bool on[FLAT_GROUP];
 #pragma unroll
         for (int j = 0; j < FLAT_GROUP; ++j) {
@@ -500,13 +523,13 @@ __global__ void __launch_bounds__(256) k_flat(DevState S) {
             const int64_t i = cj * 64 + lane;
             on[j] = k + j < nch && i < nb;
             l[j] = on[j] ? tab[i] : 0;
-            sn[j] = on[j] ? snp[i] : 0;
+            b[j] = on[j] ? hb[i] : 0;
         }
 #pragma unroll
         for (int j = 0; j < FLAT_GROUP; ++j) {
             int fail = 0;
             if (l[j] != 0) {
-                const uint64_t H = static_cast<uint64_t>(l[j] - sn[j]) >> sh;
+                const uint64_t H = stage_visits(l[j], b[j], sh);
                 fail = static_cast<unsigned __int128>(static_cast<uint64_t>(P.flat_den)) * H * n < rhs;
             }
             if (__any(fail)) {
@@ -521,7 +544,7 @@ __global__ void __launch_bounds__(256) k_flat(DevState S) {
 // ------------------------------------------------------------------ stage
 // Per problem, at an interval boundary.  sync 0 (the paper, Sec. 2): when
 // every walker is flat all windows move to the next stage together (ln f
-// halves; H restarts from zero through a new snapshot of ln g); flatness at
+// halves; H restarts from zero through a new stage base); flatness at
 // the last stage ends the problem.  sync 1: each window whose walkers are all
 // flat averages their ln g (k_average) and moves on alone; its last stage
 // ends it and its walkers stop; the problem ends with its last window.
@@ -580,7 +603,7 @@ __global__ void k_stage(DevState S) {
                 bool all = true;
                 for (int a = 0; a < P.W; ++a) all = all && (S.flag[g0 + a] != 0);
                 if (all) {
-                    S.adv[wi] = 1;  // average (and, if it goes on, take a new snapshot)
+                    S.adv[wi] = 1;  // average (and, if it goes on, take a new stage base)
                     if (S.stage[wi] == P.K) {
                         S.wdone[wi] = 1;
                     } else {
@@ -656,15 +679,19 @@ __global__ void __launch_bounds__(256) k_average(DevState S) {
     if (static_cast<int>(threadIdx.x) < W) S.nseen[g0 + threadIdx.x] = cnt[0];
 }
 
-// Snapshot of ln g for the walkers of windows that just ended a stage: one
-// workgroup per walker, a coalesced copy of its table.
+// New stage base for the walkers of windows that just ended a stage (stage s
+// now holds the new one): one workgroup per walker, a coalesced pass over its
+// table, and its audit epoch restarts with the stage.
 __global__ void __launch_bounds__(256) k_snapshot(DevState S) {
     const int64_t g = blockIdx.x;
     const WDesc d = S.wd[g];
     if (!S.adv[d.gwin]) return;
+    const int sh = S.pd[d.prob].K - S.stage[d.gwin];
     const int64_t* src = S.lng + d.table_off;
-    int64_t* dst = S.snap + d.table_off;
-    for (uint32_t i = threadIdx.x; i < d.nbins; i += blockDim.x) dst[i] = src[i];
+    uint32_t* dst = S.hb + d.table_off;
+    for (uint32_t i = threadIdx.x; i < d.nbins; i += blockDim.x)
+        dst[i] = static_cast<uint32_t>(static_cast<uint64_t>(src[i]) >> sh);
+    if (threadIdx.x == 0) S.aud[g] = 0;
 }
 
 // ------------------------------------------------------------------ exchange
@@ -860,8 +887,8 @@ hipError_t sweep_setup() {
     return hipSuccess;
 }
 
-hipError_t launch_flat(const DevState& S, hipStream_t st) {
-    hipLaunchKernelGGL(k_flat, dim3(blocks_for(S.n_walk, 4)), dim3(256), 0, st, S);
+hipError_t launch_flat(const DevState& S, hipStream_t st, int audit_only) {
+    hipLaunchKernelGGL(k_flat, dim3(blocks_for(S.n_walk, 4)), dim3(256), 0, st, S, audit_only);
     return hipGetLastError();
 }
 

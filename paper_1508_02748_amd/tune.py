@@ -78,7 +78,7 @@ def _shape_candidates(plan):
 def _with(base, **kw):
     d = dict(form=FORM_BATCHED, walkers_per_wg=base.walkers_per_wg, graph_intervals=base.graph_intervals,
              grid_waves_per_cu=base.grid_waves_per_cu, walkers_per_wave=base.walkers_per_wave,
-             table_layout=base.table_layout, profile=0)
+             table_layout=base.table_layout, audit_shift=base.audit_shift, profile=0)
     d.update(kw)
     return Tuning(**d)
 

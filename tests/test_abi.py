@@ -45,7 +45,7 @@ def test_plan_validation_and_windows_on_host():
 
     for bad in (dict(L=5), dict(L=2), dict(L=66), dict(L=16, n_windows=0), dict(L=16, overlap=(4, 4)),
                 dict(L=16, walkers_per_window=0), dict(L=16, walkers_per_window=257), dict(L=16, k_final=41),
-                dict(L=16, flat=(6, 5)), dict(L=16, interval=0), dict(L=16, init=2),
+                dict(L=16, flat=(6, 5)), dict(L=16, interval=0), dict(L=16, interval=2 ** 30 + 1), dict(L=16, init=2),
                 dict(L=16, overlap=(-1, 4)), dict(L=16, flat=(1, 0)), dict(L=16, stage_sync=2)):
         st, h = create(**bad)
         assert st == R.REWL_EINVAL, bad
@@ -59,14 +59,41 @@ def test_plan_validation_and_windows_on_host():
             assert (lo.value, hi.value) == window(256, 8, 3, 4, w)
         sizes = (C.c_size_t * 3)()
         assert L.rewl_plan_buffer_sizes(h, sizes) == 0
-        # ln g and snapshot tables, 8 bytes per bin, in 4x4 tiles of (e, m), 4 walkers per window
+        # ln g (8 bytes per bin) and stage base (4 bytes) tables in 4x4 tiles of (e, m), 4 walkers per window
         tiles = sum(-(-(window(256, 8, 3, 4, w)[1] - window(256, 8, 3, 4, w)[0] + 1) // 4) * -(-257 // 4)
                     for w in range(8))
         bins = tiles * 16 * 4
-        assert sizes[0] >= bins * 16 and sizes[0] < bins * 16 + 256
+        assert sizes[0] >= bins * 12 and sizes[0] < bins * 12 + 256
         # calls needing device buffers fail cleanly before bind
         assert L.rewl_init(h) == R.REWL_ESTATE
         assert L.rewl_run(h, 1) == R.REWL_ESTATE
+    finally:
+        L.rewl_plan_destroy(h)
+
+
+def test_audit_shift_and_fixed_tuning_fields_on_host():
+    """audit_shift is 0 (2^30) or 1..30, the interval must fit in one audit period, and neither the
+    audit shift nor the table layout of a plan can change after it is created."""
+    R, L = _lib()
+
+    def create(tn, interval=64):
+        arr = (R._Problem * 1)(R.Problem(L=8, interval=interval)._c())
+        h = C.c_void_p()
+        return L.rewl_plan_create(arr, 1, C.byref(tn._c()), C.byref(h)), h
+
+    for a, X, ok in ((0, 2 ** 30, True), (30, 2 ** 30, True), (6, 64, True), (6, 65, False), (31, 64, False),
+                     (-1, 64, False)):
+        st, h = create(R.Tuning(audit_shift=a), X)
+        assert (st == R.REWL_OK) == ok, (a, X)
+        if st == R.REWL_OK:
+            L.rewl_plan_destroy(h)
+    st, h = create(R.Tuning(audit_shift=6, table_layout=R.LAYOUT_BAND))
+    assert st == R.REWL_OK
+    try:
+        assert L.rewl_set_tuning(h, C.byref(R.Tuning(audit_shift=6, table_layout=R.LAYOUT_BAND,
+                                                      walkers_per_wg=128)._c())) == R.REWL_OK
+        assert L.rewl_set_tuning(h, C.byref(R.Tuning(audit_shift=7, table_layout=R.LAYOUT_BAND)._c())) == R.REWL_EINVAL
+        assert L.rewl_set_tuning(h, C.byref(R.Tuning(audit_shift=6)._c())) == R.REWL_EINVAL
     finally:
         L.rewl_plan_destroy(h)
 
@@ -137,7 +164,7 @@ def test_plan_create_fuzz_against_the_window_formula():
                 total += -(-(hi - lo + 1) // 4) * -(-(N + 1) // 4) * 16 * W
             sizes = (C.c_size_t * 3)()
             assert L.rewl_plan_buffer_sizes(h, sizes) == 0
-            assert total * 16 <= sizes[0] < total * 16 + 256
+            assert total * 12 <= sizes[0] < total * 12 + 256
             assert sizes[1] >= nw * W * Ls * ((Ls + 31) // 32) * 4
         finally:
             L.rewl_plan_destroy(h)
@@ -167,6 +194,6 @@ def test_split_validation_on_host():
         assert L.rewl_plan_buffer_sizes(h, sizes) == 0
         bins = sum(-(-65 // 4) * -(-(window(64, 3, 1, 2, w)[1] - window(64, 3, 1, 2, w)[0] + 1) // 4) * 16 * 2
                    for w in range(3))
-        assert bins * 16 <= sizes[0] < bins * 16 + 256
+        assert bins * 12 <= sizes[0] < bins * 12 + 256
     finally:
         L.rewl_plan_destroy(h)

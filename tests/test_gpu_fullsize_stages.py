@@ -1,5 +1,5 @@
 """Full-size parity through stage changes (the paths behind the measured
-configurations): stage advance, the snapshot copy that restarts H, the
+configurations): stage advance, the new stage base that restarts H, the
 resumable multi-chunk flatness scan, and the headroom bookkeeping, at the
 32 x 32, mixed-L and 64 x 64 shapes, in the batched and the plain form and in
 both table layouts.
@@ -68,12 +68,13 @@ def test_64x64_stage_advance_every_boundary(layout):
 
 
 @pytest.mark.slow
-def test_16x16_real_flatness_through_two_stage_changes():
+def test_16x16_real_flatness_through_two_stage_changes(capsys):
     """The 16 x 16 REWL problem (8 windows x 4 walkers, X = 10^4) under a real flatness rule until
     both sides have reached stage 2.  50 % flatness instead of 80 % so that the oracle gets there
     in minutes (about 1.1e4 intervals, 3.6e9 trials; 80 % needs 2.9e4).  Every walker is compared
     after every boundary for 64 boundaries from the first stage change, then every 64 boundaries,
-    and again at the second stage change and at the end."""
+    and again at the second stage change and at the end.  It runs about three minutes, so it
+    reports its progress past the output capture."""
     R = _R()
     p = R.Problem(L=16, n_windows=8, overlap=(3, 4), walkers_per_window=4, k_final=20, interval=10_000, seed=0,
                   flat=(1, 2))
@@ -92,6 +93,9 @@ def test_16x16_real_flatness_through_two_stage_changes():
             _say(f"first stage change at interval {k}")
         if first is not None:
             compare(plan, 0, o)
+        if k % 1024 < step:
+            with capsys.disabled():
+                print(f"[16x16 real flatness] interval {k}, stage {o.info()['stage']}", flush=True)
         assert k < 20000
     _say(f"stage 2 at interval {k}")
     assert o.info()["stage"] == 2

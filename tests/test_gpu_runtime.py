@@ -98,6 +98,77 @@ def test_int64_headroom_guard_reports_overflow(form):
     assert ei.value.status == R.REWL_EOVERFLOW
 
 
+def _first_audit_failure(p, a, max_intervals):
+    """Boundary (1-based) at which the audit of the 32-bit stage counts must stop the run: the first
+    whose pre-boundary histogram (oracle) holds a bin with 2^(a+1) visits in the current stage.
+    With interval = 2^a every boundary audits every walker.  None if the run ends first."""
+    o = _oracle_of(p)
+    for k in range(1, max_intervals + 1):
+        if o.info()["done"]:
+            return None, o, k - 1
+        o.sweep(p.interval)
+        hs = [o.walker(g)["H"] for g in range(o.n_walkers)
+              if not o.window_state(g // p.walkers_per_window)[1]]
+        if hs and max(int(h.max()) for h in hs) >= 2 ** (a + 1):
+            return k, o, k
+        o.boundary()
+    return None, o, max_intervals
+
+
+@pytest.mark.parametrize("form", ["batched", "plain"])
+def test_stage_count_audit_stops_the_run_where_a_count_reaches_the_limit(form):
+    """The stage visit counts are kept modulo 2^32 (a 32-bit stage base per bin).  An audit at the
+    first boundary after each 2^a stage trials stops the run once some bin has 2^(a+1) visits in
+    one stage, which keeps every count below 2^32.  With a = 4, 16-trial intervals and a stage
+    that never ends (100 % flatness), the run must stop at exactly the boundary the oracle's
+    histogram predicts, and not before."""
+    R = _R()
+    a = 4
+    p = R.Problem(L=4, n_windows=1, walkers_per_window=2, k_final=10, flat=(1, 1), interval=2 ** a, seed=3)
+    first, _, _ = _first_audit_failure(p, a, 1000)
+    assert first is not None and first > 10
+    tn = R.Tuning(form=R.FORM_PLAIN, audit_shift=a) if form == "plain" else R.Tuning(graph_intervals=1, audit_shift=a)
+    _say(f"case: stage-count audit, a = {a}, {form} form, expected stop at boundary {first}")
+    plan = R.Plan([p], tn)
+    plan.init()
+    for k in range(1, first):
+        plan.run(1)
+        plan.query()
+    plan.run(1)
+    with pytest.raises(R.RewlError) as ei:
+        plan.query()
+    assert ei.value.status == R.REWL_EOVERFLOW
+
+
+def test_stage_count_audit_restarts_with_each_stage():
+    """Counts restart at every stage change (new stage base, audit epoch back to zero): at a = 7 no
+    stage of this run gives a bin 256 visits, though the walkers make ~40,000 trials each, and the
+    run ends bit-exact with the oracle; at a = 6 it stops where the oracle's histogram first
+    reaches 128 visits in one stage."""
+    R = _R()
+    base = dict(L=4, n_windows=2, overlap=(1, 2), walkers_per_window=2, k_final=6, flat=(1, 2), seed=5)
+    p7 = R.Problem(interval=2 ** 7, **base)
+    first, o, k_end = _first_audit_failure(p7, 7, 5000)
+    assert first is None and o.info()["done"]
+    _say(f"case: stage-count audit a = 7, run to its end ({k_end} intervals)")
+    plan = R.Plan([p7], R.Tuning(graph_intervals=4, audit_shift=7))
+    plan.init()
+    plan.run(k_end + 3)
+    compare(plan, 0, o)
+    p6 = R.Problem(interval=2 ** 6, **base)
+    first, _, _ = _first_audit_failure(p6, 6, 5000)
+    assert first is not None
+    _say(f"case: stage-count audit a = 6, expected stop at boundary {first}")
+    plan = R.Plan([p6], R.Tuning(graph_intervals=1, audit_shift=6))
+    plan.init()
+    plan.run(first - 1)
+    plan.query()
+    plan.run(1)
+    with pytest.raises(R.RewlError) as ei:
+        plan.query()
+    assert ei.value.status == R.REWL_EOVERFLOW
+
+
 def test_destroyed_plan_leaves_no_kernel_writing_freed_memory():
     """rewl_plan_destroy (Plan.close / del) waits for the plan's stream: after a long enqueued run
     and an immediate delete, a tensor that the caching allocator hands the same memory must keep

@@ -124,24 +124,25 @@ VALU_PEAK_SLOTS = 256 * 64 * 2.4e9
 # device copy), by (workload, replicas, table layout, walkers per workgroup, grid waves per CU,
 # walkers per wavefront); measured on the current sweep kernel with rocprofv3 --pmc.  Other
 # shapes report null.
-TRAFFIC_BYTES = {("c4", 133, 1, 256, 4, 0): 42.56e9}
+TRAFFIC_BYTES = {("c4", 133, 1, 256, 4, 0): 42.56e9, ("c4", 177, 1, 256, 4, 0): 68.26e9}
 # Share of the chip's VALU cycles the sweep keeps busy by the counters (4 x SQ_ACTIVE_INST_VALU
 # over 1024 SIMDs x GRBM_GUI_ACTIVE cycles per XCD), same keys; null where not measured.
-VALU_BUSY = {("c4", 133, 1, 256, 4, 0): 0.143}
+VALU_BUSY = {("c4", 133, 1, 256, 4, 0): 0.143, ("c4", 177, 1, 256, 4, 0): 0.184}
 
 
 def launch_key(workload, replicas, layout, n_walk, wg, gw, wpw, n_cu=256):
-    """Key of the measured tables above.  Grids of several `gw` are the same launch when every
-    tile of walkers gets its own workgroup (the persistent cap does not bind): those share the
-    entry measured at the smallest such gw."""
+    """Key of the measured tables above for this launch.  Shapes that differ only in `gw` are the
+    same launch when both persistent grids give every tile of walkers its own workgroup (the cap
+    does not bind): such a shape shares the entry measured for the other."""
     per = (wg // 64) * (wpw or 64)
     tiles = -(-n_walk // per)
-    for g in range(1, 65):
-        if g >= gw:
-            break
-        if max(1, g * n_cu * 64 // wg) >= tiles and (workload, replicas, layout, wg, g, wpw) in TRAFFIC_BYTES:
-            if gw == 0 or max(1, gw * n_cu * 64 // wg) >= tiles:
-                return (workload, replicas, layout, wg, g, wpw)
+
+    def grid(g):
+        return tiles if g <= 0 else min(tiles, max(1, g * n_cu * 64 // wg))
+
+    for k in TRAFFIC_BYTES:
+        if k[:4] == (workload, replicas, layout, wg) and k[5] == wpw and grid(k[4]) == grid(gw):
+            return k
     return (workload, replicas, layout, wg, gw, wpw)
 
 

@@ -74,10 +74,11 @@ def full_run(R, torch, replicas, which="c1"):
     form (same final state, so the same final ln f), and `replicas` independent copies in one
     batched plan; trials per second from the first sweep to the boundary where the last problem
     ends."""
-    def to_end(plan, chunk):
+    def to_end(plan, chunk, label):
         plan.stream.synchronize()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        t_log = t0
         n = 0
         while True:
             plan.run(chunk)
@@ -85,16 +86,20 @@ def full_run(R, torch, replicas, which="c1"):
             q = plan.query()
             if q["done"].all():
                 break
+            if time.perf_counter() - t_log > 30:
+                t_log = time.perf_counter()
+                log(f"[full-run] {label}: {n} intervals, lowest stage {int(q['stage'].min())}, "
+                    f"{int(q['done'].sum())} of {len(q['done'])} problems done")
         return time.perf_counter() - t0, n, q
     cfg, text = FULL_RUN[which]
     out = {"workload": text}
     one = problems(1, R, cfg)
     pp = R.Plan(one, R.Tuning(form=R.FORM_PLAIN))
     pp.init()
-    Tp, _, qp = to_end(pp, 16)
+    Tp, _, qp = to_end(pp, 16, "plain")
     pb = R.Plan(one, R.Tuning(graph_intervals=16))
     pb.init()
-    Tb, _, qb = to_end(pb, 16)
+    Tb, _, qb = to_end(pb, 16, "batched")
     same = all(bool((pp.walker(0, w, a)["lng"] == pb.walker(0, w, a)["lng"]).all())
                for w in range(cfg["n_windows"]) for a in range(cfg["walkers_per_window"]))
     n1 = cfg["n_windows"] * cfg["walkers_per_window"]
@@ -107,7 +112,7 @@ def full_run(R, torch, replicas, which="c1"):
     del pp, pb
     plan = R.Plan(problems(replicas, R, cfg), R.Tuning(graph_intervals=16))
     plan.init()
-    T, n, q = to_end(plan, 256)
+    T, n, q = to_end(plan, 256, f"{replicas} replicas")
     total = int(q["trials"].sum()) * n1
     out.update({"replicas": replicas, "batch_s": T, "batch_intervals": n, "batch_trials": total,
                 "batch_value": total / T, "unit": "spin-flip attempts/s",

@@ -233,7 +233,7 @@ def main():
     ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--replicas", type=int, default=0,
                     help="independent replicas of the workload's problem set (0 = its default, or as many as fit)")
-    ap.add_argument("--layout", type=int, default=-1, help="table layout: 0 dense, 1 band, -1 = choose by timing")
+    ap.add_argument("--layout", type=int, default=-1, help="table layout: 0 dense, 1 band, 2 dense packed, 3 band packed, -1 = choose by timing")
     ap.add_argument("--no-extras", action="store_true", help="skip the 16x16 and mixed-L workloads")
     ap.add_argument("--extra-steps", type=int, default=10)
     ap.add_argument("--no-autotune", action="store_true")
@@ -285,15 +285,20 @@ def main():
     # ---------------- table layout and replica count
     free, total = torch.cuda.mem_get_info(0)
     budget = free - MEM_SPARE
+    # replicas beyond one wavefront of walkers per SIMD would put a second wavefront on some
+    # SIMDs, which then take twice as long
+    walkers_per_rep = sum(c["n_windows"] * c["walkers_per_window"] for c in unit)
+    one_wave_per_simd = max(1, 4 * torch.cuda.get_device_properties(0).multi_processor_count * 64 // walkers_per_rep)
     layout_report = None
     fit = None
     if args.layout >= 0:
         layout = args.layout
     else:
-        layout, fit, layout_report = choose_layout(lambda r: problems(r, R, unit), budget=budget, device=dev)
+        layout, fit, layout_report = choose_layout(lambda r: problems(r, R, unit), budget=budget, device=dev,
+                                                   max_replicas=one_wave_per_simd)
     per_rep = R.plan_bytes(problems(1, R, unit), layout)
     if args.replicas <= 0:
-        args.replicas = default_r if default_r > 0 else (fit or max(1, budget // per_rep))
+        args.replicas = default_r if default_r > 0 else (fit or max(1, min(one_wave_per_simd, budget // per_rep)))
     log(f"[bench] {args.workload}: layout {layout}, {per_rep / 2**30:.3f} GiB per replica, "
         f"{args.replicas} replicas ({free / 2**30:.0f} GiB free)")
 
@@ -415,7 +420,7 @@ def main():
         "warmup": W, "ms_per_step": T / K * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": f"{wl_text} x {args.replicas} independent replicas, batched form",
-                   "tuning": tuned, "table_layout": ["dense", "band"][layout],
+                   "tuning": tuned, "table_layout": ["dense", "band", "dense_packed", "band_packed"][layout],
                    "layout_probe": layout_report, "autotune": tune_report,
                    "replicas": args.replicas, "walkers": n_walk, "wavefronts": waves,
                    "bytes_per_replica": per_rep, "trials_per_walker_per_step": X,

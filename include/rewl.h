@@ -138,17 +138,19 @@ typedef struct {
                                  a small batch over more CUs; 0 = 64 */
     int32_t table_layout;     /* REWL_LAYOUT_DENSE or REWL_LAYOUT_BAND (below); fixed when
                                  the plan is created */
-    int32_t audit_shift;      /* the 32-bit stage visit counts are audited once per
-                                 2^audit_shift stage trials of a walker; 0 = 30, else
-                                 1..30; every interval must be at most 2^audit_shift.
+    int32_t audit_shift;      /* the stage visit counts are audited once per
+                                 2^audit_shift stage trials of a walker; 0 = 30 (24 for
+                                 packed layouts), else 1..30 (1..24); every interval
+                                 must be at most 2^audit_shift.
                                  An audit stops the run (REWL_EOVERFLOW) once a bin has
                                  2^(audit_shift + 1) visits in one stage, so a small
                                  value only tests that guard.  Fixed when the plan is
                                  created. */
 } rewl_tuning;
 
-/* How each walker's tables are stored (rewl_tuning.table_layout).  Both
+/* How each walker's tables are stored (rewl_tuning.table_layout).  All
  * layouts hold the same values; they differ in memory and addressing only.
+ * Bit 0 selects the band, bit 1 packed words.
  *   REWL_LAYOUT_DENSE: every bin of the window's rectangle.
  *   REWL_LAYOUT_BAND (energy split): each row of 4 energy bins keeps only
  *     the magnetization band [ceil(e/2), N - ceil(e/2)] of its lowest energy
@@ -157,15 +159,26 @@ typedef struct {
  *     width of its widest row.  (magnetization split) each window keeps only
  *     the energy rows up to 2 k_max, k_max the largest minority-spin count
  *     of its magnetization bins.  About half the memory of the dense layout
- *     over all windows. */
-enum { REWL_LAYOUT_DENSE = 0, REWL_LAYOUT_BAND = 1 };
+ *     over all windows.
+ *   ..._PACKED: one 64-bit word per bin (8 B instead of 12) holding ln g in
+ *     bits 63..26 and a 26-bit stage base in bits 25..0.  Needs k_final <= 24
+ *     and interval <= 2^24 (audit_shift <= 24, default 24); a run stops with
+ *     REWL_EOVERFLOW once some ln g reaches 2^37 units (at least 8192 in ln g)
+ *     or a bin has 2^(audit_shift + 1) visits in one stage. */
+enum {
+    REWL_LAYOUT_DENSE = 0,
+    REWL_LAYOUT_BAND = 1,
+    REWL_LAYOUT_DENSE_PACKED = 2,
+    REWL_LAYOUT_BAND_PACKED = 3
+};
 
 /* Buffers the caller provides (device memory). */
 enum {
     REWL_BUF_TABLES = 0,  /* ln g (int64, 8 B per bin) of each walker's window table
                              (4 x 4 tiles of (e, m)), then the stage base (uint32,
                              4 B per bin, same bin order): the stage's visit count
-                             is H = (ln g >> (K - s)) - base mod 2^32; 12 B per bin */
+                             is H = (ln g >> (K - s)) - base mod 2^32; 12 B per bin.
+                             Packed layouts: one word per bin, 8 B. */
     REWL_BUF_SPINS = 1,   /* bit-packed configurations */
     REWL_BUF_STATE = 2,   /* descriptors, walker and problem state, scratch */
     REWL_NBUF = 3

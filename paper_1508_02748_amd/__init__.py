@@ -25,8 +25,8 @@ REWL_OK, REWL_EINVAL, REWL_ENOMEM, REWL_EDEVICE, REWL_ESTATE, REWL_EOVERFLOW, RE
 FORM_BATCHED, FORM_PLAIN = 0, 1
 SYNC_PROBLEM, SYNC_WINDOW = 0, 1
 SPLIT_ENERGY, SPLIT_MAGNETIZATION, SPLIT_BOTH = 0, 1, 2
-LAYOUT_DENSE, LAYOUT_BAND = 0, 1
-LAYOUTS = (LAYOUT_DENSE, LAYOUT_BAND)
+LAYOUT_DENSE, LAYOUT_BAND, LAYOUT_DENSE_PACKED, LAYOUT_BAND_PACKED = 0, 1, 2, 3
+LAYOUTS = (LAYOUT_DENSE, LAYOUT_BAND, LAYOUT_DENSE_PACKED, LAYOUT_BAND_PACKED)
 NBUF = 3
 
 

@@ -42,7 +42,7 @@ namespace {
 
 __device__ __forceinline__ int64_t lng_at(const DevState& S, const WDesc& d, int er, int mc) {
     const int64_t i = table_index_or_none(d, d.e0 + er, d.m0 + mc);
-    return i < 0 ? 0 : S.lng[d.table_off + i];
+    return i < 0 ? 0 : rewl::lng_at(S, d.table_off + static_cast<uint64_t>(i));
 }
 
 struct GeoView {

@@ -229,8 +229,8 @@ rewl_status validate_tuning(const rewl_tuning& tn) {
     if (tn.profile != 0 && tn.profile != 1) return fail(REWL_EINVAL, "profile must be 0 or 1");
     if (tn.walkers_per_wave < 0 || tn.walkers_per_wave > 64) return fail(REWL_EINVAL, "walkers_per_wave 0..64");
     if (tn.profile && tn.form != REWL_FORM_BATCHED) return fail(REWL_EINVAL, "profiling times the batched form");
-    if (tn.table_layout != REWL_LAYOUT_DENSE && tn.table_layout != REWL_LAYOUT_BAND)
-        return fail(REWL_EINVAL, "table_layout must be REWL_LAYOUT_DENSE or REWL_LAYOUT_BAND");
+    if (tn.table_layout < REWL_LAYOUT_DENSE || tn.table_layout > REWL_LAYOUT_BAND_PACKED)
+        return fail(REWL_EINVAL, "table_layout must be one of the REWL_LAYOUT_ values");
     if (tn.audit_shift < 0 || tn.audit_shift > H_AUDIT_SHIFT) return fail(REWL_EINVAL, "audit_shift 0..30");
     return REWL_OK;
 }
@@ -242,7 +242,8 @@ DevState make_state(rewl_plan* P) {
     S.pd = reinterpret_cast<const PDesc*>(st + P->off_pd);
     S.pairs = reinterpret_cast<const PairDesc*>(st + P->off_pairs);
     S.lng = static_cast<int64_t*>(P->buf[REWL_BUF_TABLES]);
-    S.hb = reinterpret_cast<uint32_t*>(S.lng + P->n_bins);
+    S.packed = (P->layout & LAYOUT_PACKED) ? 1 : 0;
+    S.hb = S.packed ? nullptr : reinterpret_cast<uint32_t*>(S.lng + P->n_bins);
     S.spins = static_cast<uint32_t*>(P->buf[REWL_BUF_SPINS]);
     S.e = reinterpret_cast<int32_t*>(st + P->off_e);
     S.m = reinterpret_cast<int32_t*>(st + P->off_m);
@@ -267,7 +268,7 @@ DevState make_state(rewl_plan* P) {
     S.n_prob = static_cast<int32_t>(P->pd.size());
     S.n_pairs = static_cast<int32_t>(P->pairs.size());
     S.n_win = P->n_win;
-    S.audit_shift = P->tune.audit_shift > 0 ? P->tune.audit_shift : H_AUDIT_SHIFT;
+    S.audit_shift = P->tune.audit_shift > 0 ? P->tune.audit_shift : (S.packed ? H_AUDIT_SHIFT_PACKED : H_AUDIT_SHIFT);
     return S;
 }
 
@@ -513,8 +514,14 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
     if (tn.audit_shift > 0 && X > (1ll << tn.audit_shift))
         return fail(REWL_EINVAL, "the interval exceeds 2^audit_shift trials");
 
-    if (tn.table_layout == REWL_LAYOUT_BAND && problems[0].split == REWL_SPLIT_BOTH)
+    if ((tn.table_layout & REWL_LAYOUT_BAND) && problems[0].split == REWL_SPLIT_BOTH)
         return fail(REWL_EINVAL, "the band layout applies to one-coordinate splits");
+    if (tn.table_layout & LAYOUT_PACKED) {
+        for (int i = 0; i < n_problems; ++i)
+            if (problems[i].k_final > MAX_K_PACKED) return fail(REWL_EINVAL, "packed tables need k_final <= 24");
+        if (X > (1ll << H_AUDIT_SHIFT_PACKED)) return fail(REWL_EINVAL, "packed tables need an interval <= 2^24");
+        if (tn.audit_shift > H_AUDIT_SHIFT_PACKED) return fail(REWL_EINVAL, "packed tables need audit_shift <= 24");
+    }
 
     rewl_plan* P = new (std::nothrow) rewl_plan();
     if (!P) return fail(REWL_ENOMEM, "plan allocation");
@@ -558,7 +565,7 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
             // stored rows and tile columns of the window's tables
             int rows = R.ehi - R.elo + 1;
             uint32_t ntm = static_cast<uint32_t>((R.mhi - R.mlo + 1 + TILE_M - 1) / TILE_M);
-            const bool band = P->layout == REWL_LAYOUT_BAND && q.split == REWL_SPLIT_ENERGY;
+            const bool band = (P->layout & REWL_LAYOUT_BAND) && q.split == REWL_SPLIT_ENERGY;
             if (band) {
                 // widest tile row of the band (the lowest one, since the band narrows with e)
                 uint32_t widest = 0;
@@ -568,7 +575,7 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
                     widest = std::max<uint32_t>(widest, static_cast<uint32_t>(c1 - c0 + 1));
                 }
                 ntm = widest;
-            } else if (P->layout == REWL_LAYOUT_BAND && q.split == REWL_SPLIT_MAGNETIZATION) {
+            } else if ((P->layout & REWL_LAYOUT_BAND) && q.split == REWL_SPLIT_MAGNETIZATION) {
                 int kmax = 0;
                 for (int m = R.mlo; m <= R.mhi; ++m) kmax = std::max(kmax, std::min(m, d.N - m));
                 rows = std::min(d.N, 2 * kmax) + 1;
@@ -639,7 +646,9 @@ rewl_status rewl_plan_create(const rewl_problem* problems, int32_t n_problems, c
     P->off_xr = take(np * 8);
     P->off_xon = take(np * 4);
     P->off_cnt = take(16);
-    P->sizes[REWL_BUF_TABLES] = align_up(bins * (sizeof(int64_t) + sizeof(uint32_t)), A);
+    // ln g and stage base: one packed word per bin, or an int64 table and a uint32 table
+    const size_t per_bin = (tn.table_layout & LAYOUT_PACKED) ? sizeof(int64_t) : sizeof(int64_t) + sizeof(uint32_t);
+    P->sizes[REWL_BUF_TABLES] = align_up(bins * per_bin, A);
     P->sizes[REWL_BUF_SPINS] = align_up(words * 4, A);
     P->sizes[REWL_BUF_STATE] = o;
     *out = P;
@@ -857,7 +866,9 @@ rewl_status rewl_query(rewl_plan* P, int32_t* stage_out, int32_t* done_out, int6
     }
     if (cnt[1] & ERR_OVERFLOW) return fail(REWL_EOVERFLOW, "ln g would exceed 2^62 units");
     if (cnt[1] & ERR_HWRAP)
-        return fail(REWL_EOVERFLOW, "a bin has 2^31 visits in one stage: the 32-bit stage count would wrap");
+        return fail(REWL_EOVERFLOW, "a bin reached the audit limit of visits in one stage: its stage count could wrap");
+    if (cnt[1] & ERR_PACK)
+        return fail(REWL_EOVERFLOW, "ln g reached 2^37 units, more than a packed table word holds");
     if (cnt[1] & ERR_LAYOUT) return fail(REWL_ESTATE, "an exchanged state lies outside a stored table band");
     return REWL_OK;
 }
@@ -899,16 +910,19 @@ rewl_status rewl_read_walker(rewl_plan* P, int32_t prob, int32_t w, int32_t a, i
     if ((lng || H) && cap_bins < nb) return fail(REWL_EINVAL, "cap_bins too small");
     std::vector<int64_t> tl;
     std::vector<uint32_t> ts;
+    const bool packed = P->S.packed != 0;
     std::vector<uint32_t> words;
     std::vector<int32_t> ev, mv, stage;
     std::vector<int64_t> tv;
     if (lng || H) {
         tl.resize(d.nbins);
-        ts.resize(d.nbins);
         HIPCHK(P, hipMemcpyAsync(tl.data(), P->S.lng + d.table_off, d.nbins * sizeof(int64_t),
                                  hipMemcpyDeviceToHost, P->stream), "table read");
-        HIPCHK(P, hipMemcpyAsync(ts.data(), P->S.hb + d.table_off, d.nbins * sizeof(uint32_t),
-                                 hipMemcpyDeviceToHost, P->stream), "table read");
+        if (!packed) {
+            ts.resize(d.nbins);
+            HIPCHK(P, hipMemcpyAsync(ts.data(), P->S.hb + d.table_off, d.nbins * sizeof(uint32_t),
+                                     hipMemcpyDeviceToHost, P->stream), "table read");
+        }
     }
     const size_t nwords = static_cast<size_t>(q.L) * q.row_words;
     if (spins) {
@@ -926,9 +940,11 @@ rewl_status rewl_read_walker(rewl_plan* P, int32_t prob, int32_t w, int32_t a, i
             for (int mm = 0; mm < nM; ++mm) {
                 const int64_t ti = table_index_or_none(d, R.elo + er, R.mlo + mm);
                 const size_t oi = static_cast<size_t>(er) * nM + mm;
-                if (lng) lng[oi] = ti < 0 ? 0 : tl[ti];
+                if (lng) lng[oi] = ti < 0 ? 0 : packed ? packed_lng(tl[ti]) : tl[ti];
                 if (H)
-                    H[oi] = ti < 0 ? 0 : static_cast<uint32_t>(static_cast<uint32_t>(static_cast<uint64_t>(tl[ti]) >> sh) - ts[ti]);
+                    H[oi] = ti < 0     ? 0
+                            : packed ? packed_visits(tl[ti], sh)
+                                     : static_cast<uint32_t>(static_cast<uint32_t>(static_cast<uint64_t>(tl[ti]) >> sh) - ts[ti]);
             }
     if (spins)
         for (int r = 0; r < q.L; ++r)

@@ -25,6 +25,16 @@ namespace rewl {
 // apart, no bin exceeds 2^(a+1) + 2^(a+1) <= 2^32 visits between them, and no
 // count can wrap unnoticed.
 //
+// Packed layouts keep both in one 64-bit word per bin: ln g in bits 63..26
+// (PACK_SHIFT) and a 26-bit stage base, (ln g >> (K - s)) mod 2^26, in bits
+// 25..0; 8 bytes per bin instead of 12.  Increments of ln g are multiples of
+// 2^26 in the word and leave the base alone.  The word stays a non-negative
+// int64 while ln g < 2^37 units; the sweep checks that after every increment
+// and stops the run otherwise, so differences of words never overflow.  The
+// audit period is at most 2^24 trials there (limit 2^25 visits, and counts
+// below 2^26 between audits), and K is at most 24, so 2^37 units are at least
+// 8192 in ln g.
+//
 // Both tables are stored in tiles of 4 energy rows x 4 magnetization columns
 // (16 bins; 128 bytes of ln g, one cache line), tiles row-major: a walker's
 // trial bins (e-2..e+2, m-1 / m+1) fall into about two lines instead of five.
@@ -38,7 +48,22 @@ namespace rewl {
 // energy rows 0 .. 2 k_max only (k_max the largest minority count of the
 // window's m), which needs no change of addressing.
 constexpr int TILE_E = 4, TILE_M = 4, TILE_BINS = TILE_E * TILE_M;
-enum : int32_t { LAYOUT_DENSE = 0, LAYOUT_BAND = 1 };
+enum : int32_t { LAYOUT_DENSE = 0, LAYOUT_BAND = 1, LAYOUT_PACKED = 2 };  // band and packed are bits
+
+constexpr int PACK_SHIFT = 26;
+constexpr int64_t PACK_MASK = (static_cast<int64_t>(1) << PACK_SHIFT) - 1;
+constexpr int MAX_K_PACKED = 24;
+
+// ln g of a packed word (units 2^-K).
+__host__ __device__ inline int64_t packed_lng(int64_t w) {
+    return static_cast<int64_t>(static_cast<uint64_t>(w) >> PACK_SHIFT);
+}
+
+// Visits in the current stage of a packed word, with sh = K - s.
+__host__ __device__ inline uint32_t packed_visits(int64_t w, int sh) {
+    return static_cast<uint32_t>((static_cast<uint64_t>(w) >> (PACK_SHIFT + sh)) - static_cast<uint64_t>(w)) &
+           static_cast<uint32_t>(PACK_MASK);
+}
 
 __host__ __device__ inline uint32_t tile_index(int er, int m, uint32_t ntm) {
     return ((static_cast<uint32_t>(er >> 2) * ntm + static_cast<uint32_t>(m >> 2)) << 4) |
@@ -147,13 +172,21 @@ struct DevState {
     int32_t n_pairs;
     int32_t n_win;      // windows over all problems
     int32_t audit_shift;  // stage-count audit period 2^audit_shift trials (<= H_AUDIT_SHIFT)
+    int32_t packed;       // tables hold packed words (ln g and stage base in one int64)
 };
 
-enum : int32_t { ERR_OVERFLOW = 1, ERR_LAYOUT = 2, ERR_HWRAP = 4 };
+// ln g (units 2^-K) of table entry i, in either table format.
+__host__ __device__ inline int64_t lng_at(const DevState& S, uint64_t i) {
+    return S.packed ? packed_lng(S.lng[i]) : S.lng[i];
+}
 
-// Longest audit period of the 32-bit stage visit counts, log2 of trials (see
-// the table notes); a plan may audit more often (DevState::audit_shift).
+enum : int32_t { ERR_OVERFLOW = 1, ERR_LAYOUT = 2, ERR_HWRAP = 4, ERR_PACK = 8 };
+
+// Longest audit period of the stage visit counts, log2 of trials (see the
+// table notes): 2^30 for the 32-bit stage base, 2^24 for the packed 26-bit
+// one; a plan may audit more often (DevState::audit_shift).
 constexpr int H_AUDIT_SHIFT = 30;
+constexpr int H_AUDIT_SHIFT_PACKED = 24;
 
 // Workspace of the merge of one problem.  The windows are joined in two
 // steps: first along E within each magnetization column (the windows sharing

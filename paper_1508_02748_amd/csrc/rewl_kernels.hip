@@ -320,18 +320,24 @@ __device__ __forceinline__ void pin(NoRounds&, int64_t& v, float& f) {
 // workgroup of WG lanes).  Its spins sit in LDS column `lane`; no lane touches
 // another's data, so there are no barriers.  The bin the walker occupies is
 // held in registers and written back when the walker leaves it.  SPLIT: the
-// window coordinate (0 energy, 1 magnetization, 2 both); BAND: band addressing
-// of energy-window tables.
-template <typename RowT, int SPLIT, int BAND>
+// window coordinate (0 energy, 1 magnetization, 2 both); LAYOUT bit 0: band
+// addressing of energy-window tables, bit 1: packed words (ln g in the high 38
+// bits; ln g differences then come from the words with their base bits
+// cleared, in units of 2^-(K + PACK_SHIFT)).
+template <typename RowT, int SPLIT, int LAYOUT>
 __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int lane, int WG, int64_t g,
                                              int64_t n_trials) {
+    constexpr int BAND = LAYOUT & 1;
+    constexpr bool PACKED = (LAYOUT & 2) != 0;
+    constexpr int PS = PACKED ? PACK_SHIFT : 0;
+    constexpr int64_t HI = PACKED ? ~PACK_MASK : ~static_cast<int64_t>(0);
     const WDesc d = S.wd[g];
     const int p = d.prob;
     if (S.wdone[d.gwin]) return;  // the window (or the whole problem) has finished
     const PDesc P = S.pd[p];
     const int L = P.L, K = P.K, rw = P.row_words;
     const int s = S.stage[d.gwin];
-    const int64_t inc = static_cast<int64_t>(1) << (K - s);
+    const int64_t inc = static_cast<int64_t>(1) << (K - s + PS);
     const int lo = d.lo, hi = d.hi, mlo = d.mlo, mhi = d.mhi;
     const uint64_t seed = P.seed;
     const uint32_t gid = static_cast<uint32_t>(d.gid);
@@ -352,6 +358,7 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
     uint32_t nseen = S.nseen[g];
     uint32_t cur = table_index<BAND>(d, e, m);
     int64_t lng_cur = tab[cur];
+    bool ovf = false;  // packed words: ln g reached 2^37 units
 
     // One trial with the words (sw, uw) of its Philox block; `q` (a PhiloxRun)
     // advances the next block by five rounds while the gather is in flight.
@@ -384,7 +391,7 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
         float uf = static_cast<float>(u);
         if constexpr (!std::is_same_v<std::decay_t<decltype(q)>, NoRounds>) philox_rounds<5>(q);
         pin(q, lng2, uf);
-        if (in && accept_pre(lng_cur - lng2, u, uf, K)) {
+        if (in && accept_pre((lng_cur & HI) - (lng2 & HI), u, uf, K + PS)) {
             tab[cur] = lng_cur;
             lds[(r << wsh) + lane] = row ^ (static_cast<RowT>(1) << c);
             e = e2;
@@ -394,6 +401,7 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
         }
         nseen += (lng_cur == 0) ? 1u : 0u;
         lng_cur += inc;
+        if constexpr (PACKED) ovf = ovf || lng_cur < 0;
         ++t;
     };
 
@@ -424,6 +432,7 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
         trial(blk.x, blk.y, none);
     }
     tab[cur] = lng_cur;
+    if (PACKED && ovf) atomicOr(&S.counters[1], ERR_PACK);
     S.e[g] = e;
     S.m[g] = m;
     S.t[g] = t;
@@ -444,7 +453,7 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
 // walkers in flight and so the set of table lines competing for the L2; the
 // tile-to-workgroup map is the same at every launch, so a walker stays on the
 // same XCD.
-template <typename RowT, int SPLIT, int BAND>
+template <typename RowT, int SPLIT, int LAYOUT>
 __global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int64_t g_count,
                                                int64_t n_trials, int wpw) {
     extern __shared__ unsigned char lds_raw[];
@@ -458,7 +467,7 @@ __global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int6
     const int64_t n_tiles = (g_count + per - 1) / per;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t gi = tile * per + wave * wpw + wl;
-        if (wl < wpw && gi < g_count) sweep_walker<RowT, SPLIT, BAND>(S, lds, lane, WG, g_begin + gi, n_trials);
+        if (wl < wpw && gi < g_count) sweep_walker<RowT, SPLIT, LAYOUT>(S, lds, lane, WG, g_begin + gi, n_trials);
     }
 }
 
@@ -494,13 +503,14 @@ __global__ void __launch_bounds__(256) k_flat(DevState S, int audit_only) {
     const int sh = P.K - S.stage[d.gwin];
     const uint64_t sum = static_cast<uint64_t>(S.t[g] - S.tstage[d.gwin]);
     const int64_t* tab = S.lng + d.table_off;
-    const uint32_t* hb = S.hb + d.table_off;
+    const uint32_t* hb = S.packed ? nullptr : S.hb + d.table_off;
     const int64_t nb = d.nbins;
     const uint32_t epoch = static_cast<uint32_t>(sum >> S.audit_shift);
     if (epoch != S.aud[g]) {
         const uint32_t lim = 1u << (S.audit_shift + 1);
         bool wrap = false;
-        for (int64_t i = lane; i < nb; i += 64) wrap = wrap || stage_visits(tab[i], hb[i], sh) >= lim;
+        for (int64_t i = lane; i < nb; i += 64)
+            wrap = wrap || (hb ? stage_visits(tab[i], hb[i], sh) : packed_visits(tab[i], sh)) >= lim;
         if (__any(wrap) && lane == 0) atomicOr(&S.counters[1], ERR_HWRAP);
         if (lane == 0) S.aud[g] = epoch;
     }
@@ -523,13 +533,13 @@ __global__ void __launch_bounds__(256) k_flat(DevState S, int audit_only) {
             const int64_t i = cj * 64 + lane;
             on[j] = k + j < nch && i < nb;
             l[j] = on[j] ? tab[i] : 0;
-            b[j] = on[j] ? hb[i] : 0;
+            b[j] = on[j] && hb ? hb[i] : 0;
         }
 #pragma unroll
         for (int j = 0; j < FLAT_GROUP; ++j) {
             int fail = 0;
             if (l[j] != 0) {
-                const uint64_t H = stage_visits(l[j], b[j], sh);
+                const uint64_t H = hb ? stage_visits(l[j], b[j], sh) : packed_visits(l[j], sh);
                 fail = static_cast<unsigned __int128>(static_cast<uint64_t>(P.flat_den)) * H * n < rhs;
             }
             if (__any(fail)) {
@@ -659,7 +669,7 @@ __global__ void __launch_bounds__(256) k_average(DevState S) {
         unsigned __int128 sum = 0;
         uint32_t n = 0;
         for (int a = 0; a < W; ++a) {
-            const int64_t v = S.lng[S.wd[g0 + a].table_off + i];
+            const int64_t v = lng_at(S, S.wd[g0 + a].table_off + i);
             if (v > 0) {
                 sum += static_cast<uint64_t>(v);
                 ++n;
@@ -667,7 +677,9 @@ __global__ void __launch_bounds__(256) k_average(DevState S) {
         }
         if (n == 0) continue;
         const int64_t avg = static_cast<int64_t>(sum / n);
-        for (int a = 0; a < W; ++a) S.lng[S.wd[g0 + a].table_off + i] = avg;
+        // packed: the base bits are rewritten by k_snapshot right after
+        const int64_t word = S.packed ? static_cast<int64_t>(static_cast<uint64_t>(avg) << PACK_SHIFT) : avg;
+        for (int a = 0; a < W; ++a) S.lng[S.wd[g0 + a].table_off + i] = word;
         ++seen;
     }
     cnt[threadIdx.x] = seen;
@@ -687,10 +699,18 @@ __global__ void __launch_bounds__(256) k_snapshot(DevState S) {
     const WDesc d = S.wd[g];
     if (!S.adv[d.gwin]) return;
     const int sh = S.pd[d.prob].K - S.stage[d.gwin];
-    const int64_t* src = S.lng + d.table_off;
-    uint32_t* dst = S.hb + d.table_off;
-    for (uint32_t i = threadIdx.x; i < d.nbins; i += blockDim.x)
-        dst[i] = static_cast<uint32_t>(static_cast<uint64_t>(src[i]) >> sh);
+    int64_t* src = S.lng + d.table_off;
+    if (S.packed) {
+        for (uint32_t i = threadIdx.x; i < d.nbins; i += blockDim.x) {
+            const int64_t w = src[i];
+            src[i] = (w & ~PACK_MASK) | static_cast<int64_t>((static_cast<uint64_t>(w) >> (PACK_SHIFT + sh)) &
+                                                             static_cast<uint64_t>(PACK_MASK));
+        }
+    } else {
+        uint32_t* dst = S.hb + d.table_off;
+        for (uint32_t i = threadIdx.x; i < d.nbins; i += blockDim.x)
+            dst[i] = static_cast<uint32_t>(static_cast<uint64_t>(src[i]) >> sh);
+    }
     if (threadIdx.x == 0) S.aud[g] = 0;
 }
 
@@ -736,8 +756,7 @@ __global__ void __launch_bounds__(64) k_exchange(DevState S) {
             const WDesc dA = S.wd[A], dB = S.wd[B];
             const int eA = S.e[A], mA = S.m[A], eB = S.e[B], mB = S.m[B];
             if (!in_window(P.split, dB, eA, mA) || !in_window(P.split, dA, eB, mB)) continue;
-            const int64_t* tA = S.lng + dA.table_off;
-            const int64_t* tB = S.lng + dB.table_off;
+            const uint64_t tA = dA.table_off, tB = dB.table_off;
             // both configurations are states of both windows, so every bin below is stored;
             // a bin that is not would be a layout error, reported instead of read
             const int64_t iAX = table_index_or_none(dA, eA, mA), iAY = table_index_or_none(dA, eB, mB);
@@ -746,7 +765,8 @@ __global__ void __launch_bounds__(64) k_exchange(DevState S) {
                 atomicOr(&S.counters[1], ERR_LAYOUT);
                 continue;
             }
-            const int64_t delta = tA[iAX] - tA[iAY] + tB[iBY] - tB[iBX];
+            const int64_t delta = lng_at(S, tA + iAX) - lng_at(S, tA + iAY) + lng_at(S, tB + iBY) -
+                                  lng_at(S, tB + iBX);
             const Words4 b = philox4x32_10(P.seed, r_lo, r_hi, static_cast<uint32_t>(w),
                                            (TAG_XACC << 24) | static_cast<uint32_t>(a));
             if (accept_move(delta, b.x, P.K)) {
@@ -842,17 +862,23 @@ hipError_t launch_entry(const DevState& S, int64_t cap, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Instantiations: every split with dense addressing, energy windows also with
+// band addressing, each with unpacked and packed tables.
+#define REWL_SWEEP_KERNELS(RowT)                                                                          \
+    &k_sweep<RowT, 0, 0>, &k_sweep<RowT, 0, 1>, &k_sweep<RowT, 1, 0>, &k_sweep<RowT, 2, 0>,             \
+        &k_sweep<RowT, 0, 2>, &k_sweep<RowT, 0, 3>, &k_sweep<RowT, 1, 2>, &k_sweep<RowT, 2, 2>
+
 template <typename RowT>
-void launch_sweep_t(int split, int band, dim3 grid, dim3 wg, size_t lds, hipStream_t st, const DevState& S,
+hipError_t launch_sweep_t(int split, int layout, dim3 grid, dim3 wg, size_t lds, hipStream_t st, const DevState& S,
                     int64_t g_begin, int64_t g_count, int64_t n_trials, int wpw) {
-    if (split == 0 && band)
-        hipLaunchKernelGGL((k_sweep<RowT, 0, 1>), grid, wg, lds, st, S, g_begin, g_count, n_trials, wpw);
-    else if (split == 0)
-        hipLaunchKernelGGL((k_sweep<RowT, 0, 0>), grid, wg, lds, st, S, g_begin, g_count, n_trials, wpw);
-    else if (split == 1)
-        hipLaunchKernelGGL((k_sweep<RowT, 1, 0>), grid, wg, lds, st, S, g_begin, g_count, n_trials, wpw);
-    else
-        hipLaunchKernelGGL((k_sweep<RowT, 2, 0>), grid, wg, lds, st, S, g_begin, g_count, n_trials, wpw);
+    using Kern = void (*)(DevState, int64_t, int64_t, int64_t, int);
+    static const Kern kerns[8] = {REWL_SWEEP_KERNELS(RowT)};
+    const int band = split == 0 && (layout & LAYOUT_BAND);
+    const int base = split == 0 ? band : split + 1;  // 0..3: (0, dense) (0, band) (1) (2)
+    const Kern k = kerns[base + ((layout & LAYOUT_PACKED) ? 4 : 0)];
+    DevState s_arg = S;
+    void* args[] = {&s_arg, &g_begin, &g_count, &n_trials, &wpw};
+    return hipLaunchKernel(reinterpret_cast<const void*>(k), grid, wg, args, lds, st);
 }
 
 hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int64_t n_trials,
@@ -863,25 +889,19 @@ hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int
     if (max_grid > 0 && grid > max_grid) grid = max_grid;
     const size_t lds = static_cast<size_t>(l_max) * wg * (l_max <= 32 ? sizeof(uint32_t) : sizeof(uint64_t));
     // band addressing applies to energy windows only (magnetization windows keep dense addressing)
-    const int band = layout == LAYOUT_BAND && split == 0;
-    if (l_max <= 32)
-        launch_sweep_t<uint32_t>(split, band, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
-    else
-        launch_sweep_t<uint64_t>(split, band, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
-    return hipGetLastError();
+    const hipError_t e =
+        l_max <= 32
+            ? launch_sweep_t<uint32_t>(split, layout, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw)
+            : launch_sweep_t<uint64_t>(split, layout, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t sweep_setup() {
-    const void* fns[8] = {reinterpret_cast<const void*>(&k_sweep<uint32_t, 0, 0>),
-                          reinterpret_cast<const void*>(&k_sweep<uint32_t, 0, 1>),
-                          reinterpret_cast<const void*>(&k_sweep<uint32_t, 1, 0>),
-                          reinterpret_cast<const void*>(&k_sweep<uint32_t, 2, 0>),
-                          reinterpret_cast<const void*>(&k_sweep<uint64_t, 0, 0>),
-                          reinterpret_cast<const void*>(&k_sweep<uint64_t, 0, 1>),
-                          reinterpret_cast<const void*>(&k_sweep<uint64_t, 1, 0>),
-                          reinterpret_cast<const void*>(&k_sweep<uint64_t, 2, 0>)};
-    for (const void* f : fns) {
-        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    using Kern = void (*)(DevState, int64_t, int64_t, int64_t, int);
+    const Kern fns[16] = {REWL_SWEEP_KERNELS(uint32_t), REWL_SWEEP_KERNELS(uint64_t)};
+    for (Kern f : fns) {
+        const hipError_t e =
+            hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -152,18 +152,25 @@ def autotune(plan, intervals=1, candidates=None, use_cache=True, verbose=False, 
     return best
 
 
-def choose_layout(problems_of, budget=None, probe_replicas=2, intervals=2, device="cuda:0", verbose=False):
+def choose_layout(problems_of, budget=None, probe_replicas=2, intervals=2, device="cuda:0", verbose=False,
+                  max_replicas=None):
     """Table layout for a batch of replicas of one problem set; `problems_of(r)` gives the
-    problems of r replicas.  Each layout in LAYOUTS is timed on a probe plan of `probe_replicas`
-    replicas over `intervals` intervals.  Without a memory budget the faster layout wins.  With
-    `budget` bytes, each layout's batch is as many replicas as fit, and the layout with the higher
-    expected throughput (replicas that fit / probe sweep time) wins: a smaller layout can carry
-    more walker chains.  Returns (layout, replicas or None, report).  Layouts do not change
-    results."""
+    problems of r replicas.  Each layout in LAYOUTS that the problems allow (packed words need
+    k_final <= 24) is timed on a probe plan of `probe_replicas` replicas over `intervals`
+    intervals.  Without a memory budget the fastest layout wins.  With `budget` bytes, each
+    layout's batch is as many replicas as fit, at most `max_replicas` (a batch beyond one
+    wavefront per SIMD gains nothing), and the layout with the higher expected throughput
+    (replicas / probe sweep time) wins, ties to the faster probe: a smaller layout can carry more
+    walker chains.  Returns (layout, replicas or None, report).  Layouts do not change results."""
     import torch
+    from . import RewlError
     report = {}
     for lay in LAYOUTS:
-        per = plan_bytes(problems_of(1), lay)
+        try:
+            per = plan_bytes(problems_of(1), lay)
+        except RewlError as e:
+            report[lay] = {"refused": str(e)}
+            continue
         plan = Plan(problems_of(probe_replicas), Tuning(table_layout=lay, profile=1), device=device)
         plan.init()
         plan.run(1)
@@ -173,13 +180,17 @@ def choose_layout(problems_of, budget=None, probe_replicas=2, intervals=2, devic
         del plan
         torch.cuda.empty_cache()
         fit = None if budget is None else max(0, int(budget // per))
+        if fit is not None and max_replicas is not None:
+            fit = min(fit, int(max_replicas))
         report[lay] = {"probe_sweep_ms": ms, "bytes_per_replica": per, "replicas_fit": fit}
         if verbose:
             print(f"[tune] table_layout={lay}: probe sweep {ms:.3f} ms, {per / 2**30:.3f} GiB per replica, "
                   f"{fit} replicas fit", flush=True)
+    ok = [lay for lay in LAYOUTS if "probe_sweep_ms" in report[lay]]
     if budget is None:
-        return min(LAYOUTS, key=lambda lay: report[lay]["probe_sweep_ms"]), None, report
-    best = max(LAYOUTS, key=lambda lay: report[lay]["replicas_fit"] / report[lay]["probe_sweep_ms"])
+        return min(ok, key=lambda lay: report[lay]["probe_sweep_ms"]), None, report
+    best = max(ok, key=lambda lay: (report[lay]["replicas_fit"] / report[lay]["probe_sweep_ms"],
+                                    -report[lay]["probe_sweep_ms"]))
     if report[best]["replicas_fit"] < 1:
         return LAYOUT_DENSE, 1, report
     return best, report[best]["replicas_fit"], report

@@ -98,6 +98,49 @@ def test_audit_shift_and_fixed_tuning_fields_on_host():
         L.rewl_plan_destroy(h)
 
 
+def test_packed_layouts_on_host():
+    """Packed layouts keep one 8-byte word per bin (against 12 bytes) and need k_final <= 24, an
+    interval of at most 2^24 trials and audit_shift <= 24; the band bit applies as in the unpacked
+    layouts."""
+    R, L = _lib()
+
+    def create(layout, audit_shift=0, **kw):
+        q = dict(L=16, n_windows=8, walkers_per_window=4, k_final=20, interval=10_000)
+        q.update(kw)
+        arr = (R._Problem * 1)(R.Problem(**q)._c())
+        h = C.c_void_p()
+        tn = R.Tuning(table_layout=layout, audit_shift=audit_shift)
+        return L.rewl_plan_create(arr, 1, C.byref(tn._c()), C.byref(h)), h
+
+    def tables(layout):
+        st, h = create(layout)
+        assert st == R.REWL_OK
+        sizes = (C.c_size_t * 3)()
+        assert L.rewl_plan_buffer_sizes(h, sizes) == 0
+        L.rewl_plan_destroy(h)
+        return sizes[0]
+
+    for plain, packed in ((R.LAYOUT_DENSE, R.LAYOUT_DENSE_PACKED), (R.LAYOUT_BAND, R.LAYOUT_BAND_PACKED)):
+        a, b = tables(plain), tables(packed)
+        assert abs(b * 12 - a * 8) <= 256 * 12, (plain, a, b)
+    for layout in (R.LAYOUT_DENSE_PACKED, R.LAYOUT_BAND_PACKED):
+        for kw, ok in ((dict(k_final=24), True), (dict(k_final=25), False), (dict(interval=2 ** 24), True),
+                       (dict(interval=2 ** 24 + 1), False)):
+            st, h = create(layout, **kw)
+            assert (st == R.REWL_OK) == ok, (layout, kw)
+            if st == R.REWL_OK:
+                L.rewl_plan_destroy(h)
+        for a, ok in ((24, True), (25, False)):
+            st, h = create(layout, audit_shift=a, interval=64)
+            assert (st == R.REWL_OK) == ok, (layout, a)
+            if st == R.REWL_OK:
+                L.rewl_plan_destroy(h)
+    st, h = create(4)
+    assert st == R.REWL_EINVAL
+    st, h = create(R.LAYOUT_BAND_PACKED, split=R.SPLIT_BOTH, m_windows=2, m_overlap=(1, 2))
+    assert st == R.REWL_EINVAL
+
+
 def test_mixed_interval_rejected():
     R, L = _lib()
     arr = (R._Problem * 2)(R.Problem(L=8, interval=100)._c(), R.Problem(L=8, interval=200)._c())

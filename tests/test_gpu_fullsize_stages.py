@@ -46,7 +46,7 @@ def test_32x32_and_mixed_stage_advance_every_boundary(layout):
     assert min(o.info()["stage"] for o in orcs.values()) == 10
 
 
-@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("layout", [0, 1, 3])
 def test_64x64_stage_advance_every_boundary(layout):
     R = _R()
     probs = [R.Problem(seed=500 + s, flat=(0, 1), **C4) for s in range(3)]

@@ -115,8 +115,8 @@ def _first_audit_failure(p, a, max_intervals):
     return None, o, max_intervals
 
 
-@pytest.mark.parametrize("form", ["batched", "plain"])
-def test_stage_count_audit_stops_the_run_where_a_count_reaches_the_limit(form):
+@pytest.mark.parametrize("form,layout", [("batched", 0), ("plain", 0), ("batched", 2), ("plain", 3)])
+def test_stage_count_audit_stops_the_run_where_a_count_reaches_the_limit(form, layout):
     """The stage visit counts are kept modulo 2^32 (a 32-bit stage base per bin).  An audit at the
     first boundary after each 2^a stage trials stops the run once some bin has 2^(a+1) visits in
     one stage, which keeps every count below 2^32.  With a = 4, 16-trial intervals and a stage
@@ -127,8 +127,9 @@ def test_stage_count_audit_stops_the_run_where_a_count_reaches_the_limit(form):
     p = R.Problem(L=4, n_windows=1, walkers_per_window=2, k_final=10, flat=(1, 1), interval=2 ** a, seed=3)
     first, _, _ = _first_audit_failure(p, a, 1000)
     assert first is not None and first > 10
-    tn = R.Tuning(form=R.FORM_PLAIN, audit_shift=a) if form == "plain" else R.Tuning(graph_intervals=1, audit_shift=a)
-    _say(f"case: stage-count audit, a = {a}, {form} form, expected stop at boundary {first}")
+    tn = (R.Tuning(form=R.FORM_PLAIN, audit_shift=a, table_layout=layout) if form == "plain"
+          else R.Tuning(graph_intervals=1, audit_shift=a, table_layout=layout))
+    _say(f"case: stage-count audit, a = {a}, {form} form, layout {layout}, expected stop at boundary {first}")
     plan = R.Plan([p], tn)
     plan.init()
     for k in range(1, first):
@@ -140,7 +141,8 @@ def test_stage_count_audit_stops_the_run_where_a_count_reaches_the_limit(form):
     assert ei.value.status == R.REWL_EOVERFLOW
 
 
-def test_stage_count_audit_restarts_with_each_stage():
+@pytest.mark.parametrize("layout", [0, 3])
+def test_stage_count_audit_restarts_with_each_stage(layout):
     """Counts restart at every stage change (new stage base, audit epoch back to zero): at a = 7 no
     stage of this run gives a bin 256 visits, though the walkers make ~40,000 trials each, and the
     run ends bit-exact with the oracle; at a = 6 it stops where the oracle's histogram first
@@ -151,7 +153,7 @@ def test_stage_count_audit_restarts_with_each_stage():
     first, o, k_end = _first_audit_failure(p7, 7, 5000)
     assert first is None and o.info()["done"]
     _say(f"case: stage-count audit a = 7, run to its end ({k_end} intervals)")
-    plan = R.Plan([p7], R.Tuning(graph_intervals=4, audit_shift=7))
+    plan = R.Plan([p7], R.Tuning(graph_intervals=4, audit_shift=7, table_layout=layout))
     plan.init()
     plan.run(k_end + 3)
     compare(plan, 0, o)
@@ -159,7 +161,7 @@ def test_stage_count_audit_restarts_with_each_stage():
     first, _, _ = _first_audit_failure(p6, 6, 5000)
     assert first is not None
     _say(f"case: stage-count audit a = 6, expected stop at boundary {first}")
-    plan = R.Plan([p6], R.Tuning(graph_intervals=1, audit_shift=6))
+    plan = R.Plan([p6], R.Tuning(graph_intervals=1, audit_shift=6, table_layout=layout))
     plan.init()
     plan.run(first - 1)
     plan.query()

@@ -94,6 +94,16 @@ struct WDesc {
     int32_t pad_;
 };
 
+// a * b for a, b < 2^24 (tile rows and columns never exceed 1025): one
+// full-rate 24-bit multiply on the device.
+__host__ __device__ inline uint32_t mul24(uint32_t a, uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return static_cast<uint32_t>(__umul24(a, b));
+#else
+    return a * b;
+#endif
+}
+
 // Index of bin (e, m) in a walker's table, for a bin the table stores (any
 // state of the window): BAND = 1 for the band addressing of energy windows.
 template <int BAND>
@@ -101,7 +111,8 @@ __host__ __device__ inline uint32_t table_index(const WDesc& d, int e, int m) {
     const int er = e - d.e0, mc = m - d.m0;
     if (BAND) {
         const int tr = er >> 2;
-        return ((static_cast<uint32_t>(tr) * d.ntm + static_cast<uint32_t>((mc >> 2) - band_c0(d.e0, tr))) << 4) |
+        return ((mul24(static_cast<uint32_t>(tr), d.ntm) + static_cast<uint32_t>((mc >> 2) - band_c0(d.e0, tr)))
+                << 4) |
                (static_cast<uint32_t>(er & 3) << 2) | static_cast<uint32_t>(mc & 3);
     }
     return tile_index(er, mc, d.ntm);

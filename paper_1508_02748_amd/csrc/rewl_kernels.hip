@@ -36,6 +36,11 @@ struct Words4 {
     uint32_t x, y, z, w;
 };
 
+// Three-input xor in one gfx950 instruction (v_bitop3_b32, truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32 -> 64 multiplies mixing the counter with a Weyl-incremented key.
 __device__ __forceinline__ Words4 philox4x32_10(uint64_t key, uint32_t c0, uint32_t c1,
@@ -48,8 +53,8 @@ __device__ __forceinline__ Words4 philox4x32_10(uint64_t key, uint32_t c0, uint3
         const uint32_t a_hi = __umulhi(0xD2511F53u, c0);
         const uint32_t b_lo = 0xCD9E8D57u * c2;
         const uint32_t b_hi = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = b_hi ^ c1 ^ k0;
-        const uint32_t n2 = a_hi ^ c3 ^ k1;
+        const uint32_t n0 = xor3(b_hi, c1, k0);
+        const uint32_t n2 = xor3(a_hi, c3, k1);
         c0 = n0;
         c1 = b_lo;
         c2 = n2;
@@ -253,24 +258,33 @@ __global__ void k_entry(DevState S, int64_t cap) {
 // ------------------------------------------------------------------ sweep
 // Acceptance decision identical to accept_move, reached faster: a single
 // precision estimate a of exp(x) (hardware exp2, relative error below 5e-6
-// for -23 < x < 0 including the rounding of x and u to float) decides unless
-// u lies within 1e-4 relative of a; only then is the double-precision
-// exp_neg evaluated.  Every path gives u < exp_neg(x) exactly.  The uniform
-// (u and its float rounding uf) is formed before the gathered ln g arrives,
-// and the filter has no branches: only the rare near-tie branches.
-__device__ __forceinline__ bool accept_pre(int64_t delta, double u, float uf, int K, bool& exact_path) {
+// for -23 < x < 0 including the rounding of x to float and the two roundings
+// of uf below) decides unless u lies within 1e-4 relative of a; only then is
+// the double-precision exp_neg evaluated, with u = (w + 1/2) 2^-32 formed
+// exactly in double.  Every path gives u < exp_neg(x) exactly.  The float
+// uniform uf = fl(fl(w) 2^-32 + 2^-33) (relative error below 2^-23) is formed
+// before the gathered ln g arrives, and the filter has no branches: only the
+// rare near-tie branches.
+__device__ __forceinline__ float uniform_f(uint32_t w) {
+    return __fmaf_rn(static_cast<float>(w), 0x1p-32f, 0x1p-33f);
+}
+
+__device__ __forceinline__ bool accept_pre(int64_t delta, uint32_t w, float uf, int K, bool& exact_path) {
     const double x = ldexp(static_cast<double>(delta), -K);
     const float a = __builtin_amdgcn_exp2f(static_cast<float>(x) * 1.44269504f);
     bool acc = delta >= 0 || uf < a * 0.9999f;
     const bool rej = delta <= -(static_cast<int64_t>(23) << K) || uf > a * 1.0001f;
     exact_path = !acc && !rej;
-    if (exact_path) acc = u < exp_neg(x);
+    if (exact_path) {
+        const double u = __dmul_rn(__dadd_rn(static_cast<double>(w), 0.5), 1.0 / 4294967296.0);
+        acc = u < exp_neg(x);
+    }
     return acc;
 }
 
-__device__ __forceinline__ bool accept_pre(int64_t delta, double u, float uf, int K) {
+__device__ __forceinline__ bool accept_pre(int64_t delta, uint32_t w, float uf, int K) {
     bool unused;
-    return accept_pre(delta, u, uf, K, unused);
+    return accept_pre(delta, w, uf, K, unused);
 }
 
 // First and second halves of a Philox4x32-10 evaluation, so that the next
@@ -291,8 +305,8 @@ __device__ __forceinline__ void philox_rounds(PhiloxRun& q) {
         // one 32x32 -> 64 multiply per product (low and high words together)
         const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * q.c0;
         const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * q.c2;
-        const uint32_t n0 = static_cast<uint32_t>(pb >> 32) ^ q.c1 ^ q.k0;
-        const uint32_t n2 = static_cast<uint32_t>(pa >> 32) ^ q.c3 ^ q.k1;
+        const uint32_t n0 = xor3(static_cast<uint32_t>(pb >> 32), q.c1, q.k0);
+        const uint32_t n2 = xor3(static_cast<uint32_t>(pa >> 32), q.c3, q.k1);
         q.c0 = n0;
         q.c1 = static_cast<uint32_t>(pb);
         q.c2 = n2;
@@ -387,11 +401,10 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
         // gather unconditionally (the current bin when the proposal leaves the window)
         const uint32_t idx2 = in ? table_index<BAND>(d, e2, m2) : cur;
         int64_t lng2 = tab[idx2];
-        const double u = __dmul_rn(__dadd_rn(static_cast<double>(uw), 0.5), 1.0 / 4294967296.0);
-        float uf = static_cast<float>(u);
+        float uf = uniform_f(uw);
         if constexpr (!std::is_same_v<std::decay_t<decltype(q)>, NoRounds>) philox_rounds<5>(q);
         pin(q, lng2, uf);
-        if (in && accept_pre((lng_cur & HI) - (lng2 & HI), u, uf, K + PS)) {
+        if (in && accept_pre((lng_cur & HI) - (lng2 & HI), uw, uf, K + PS)) {
             tab[cur] = lng_cur;
             lds[(r << wsh) + lane] = row ^ (static_cast<RowT>(1) << c);
             e = e2;
@@ -825,9 +838,8 @@ __global__ void k_accept_check(int K, uint64_t seed, int64_t n, double rel, unsi
     }
     target = fmin(fmax(target, 0.0), 4294967295.0);
     const uint32_t w = static_cast<uint32_t>(target);
-    const double u = __dmul_rn(__dadd_rn(static_cast<double>(w), 0.5), 1.0 / 4294967296.0);
     bool exact_path = false;
-    const bool fast = accept_pre(delta, u, static_cast<float>(u), K, exact_path);
+    const bool fast = accept_pre(delta, w, uniform_f(w), K, exact_path);
     const bool spec = accept_move(delta, w, K);
     if (fast != spec) atomicAdd(&counts[0], 1ull);
     if (exact_path) atomicAdd(&counts[1], 1ull);

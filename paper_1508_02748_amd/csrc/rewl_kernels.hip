@@ -330,6 +330,19 @@ __device__ __forceinline__ void pin(NoRounds&, int64_t& v, float& f) {
     asm volatile("" : "+v"(v), "+v"(f) : : "memory");
 }
 
+// Pins the next trial's proposal at the same point, so that its LDS reads and
+// neighbour count are made while the gather is in flight.
+__device__ __forceinline__ void pin_prop(uint32_t& k, uint32_t& bc) {
+    asm volatile("" : "+v"(k), "+v"(bc));
+}
+
+// Flips bit c of a walker's spin row in LDS in place (the row value a proposal
+// read may be older than another flip in the same row).
+__device__ __forceinline__ void xor_bit(uint32_t* row, int c) { atomicXor(row, 1u << c); }
+__device__ __forceinline__ void xor_bit(uint64_t* row, int c) {
+    atomicXor(reinterpret_cast<unsigned long long*>(row), 1ull << c);
+}
+
 // n_trials Wang-Landau trials (Eq. 1) for walker g (lane `lane` of a
 // workgroup of WG lanes).  Its spins sit in LDS column `lane`; no lane touches
 // another's data, so there are no barriers.  The bin the walker occupies is
@@ -374,11 +387,18 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
     int64_t lng_cur = tab[cur];
     bool ovf = false;  // packed words: ln g reached 2^37 units
 
-    // One trial with the words (sw, uw) of its Philox block; `q` (a PhiloxRun)
-    // advances the next block by five rounds while the gather is in flight.
-    auto trial = [&](uint32_t sw, uint32_t uw, auto& q) {
+    // The proposal of a trial: its site, the site's spin and the number of its
+    // four neighbours anti-aligned with it, and the linear indices of the five
+    // sites it reads (for the check after a flip).
+    struct Prop {
         int r, c;
-        site_rc(sw, L, r, c);
+        uint32_t bc, k;
+        int s0, s1, s2, s3, s4;
+    };
+    auto propose = [&](uint32_t sw) {
+        Prop pr;
+        site_rc(sw, L, pr.r, pr.c);
+        const int r = pr.r, c = pr.c;
         const int ru = r == 0 ? L - 1 : r - 1;
         const int rd = r == L - 1 ? 0 : r + 1;
         const int cl = c == 0 ? L - 1 : c - 1;
@@ -386,14 +406,27 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
         const RowT row = lds[(r << wsh) + lane];
         const RowT rowu = lds[(ru << wsh) + lane];
         const RowT rowd = lds[(rd << wsh) + lane];
-        const uint32_t bc = static_cast<uint32_t>(row >> c) & 1u;
-        // number of the four neighbours anti-aligned with the site
-        const uint32_t k = ((static_cast<uint32_t>(row >> cl) & 1u) ^ bc) +
-                           ((static_cast<uint32_t>(row >> cr) & 1u) ^ bc) +
-                           ((static_cast<uint32_t>(rowu >> c) & 1u) ^ bc) +
-                           ((static_cast<uint32_t>(rowd >> c) & 1u) ^ bc);
-        const int e2 = e + 2 - static_cast<int>(k);       // dE = 8 - 4k
-        const int m2 = m + 1 - 2 * static_cast<int>(bc);  // dM = -2 s
+        pr.bc = static_cast<uint32_t>(row >> c) & 1u;
+        pr.k = ((static_cast<uint32_t>(row >> cl) & 1u) ^ pr.bc) + ((static_cast<uint32_t>(row >> cr) & 1u) ^ pr.bc) +
+               ((static_cast<uint32_t>(rowu >> c) & 1u) ^ pr.bc) + ((static_cast<uint32_t>(rowd >> c) & 1u) ^ pr.bc);
+        pr.s0 = r * L + c;
+        pr.s1 = r * L + cl;
+        pr.s2 = r * L + cr;
+        pr.s3 = ru * L + c;
+        pr.s4 = rd * L + c;
+        return pr;
+    };
+
+    // One trial with the proposal `pr` (made from its site word before this
+    // trial began) and the uniform word uw.  While the table gather is in
+    // flight, `q` (a PhiloxRun) advances the next block by five rounds and the
+    // next trial's proposal is made from the spins as they are now (site word
+    // swn, or q.c0 after the rounds when from_q); a flip by this trial of one
+    // of the five sites that proposal read makes it again.  Flips are xors in
+    // LDS, so a row read before an earlier flip is never written back.
+    auto trial = [&](Prop& pr, uint32_t uw, uint32_t swn, bool more, bool from_q, auto& q) {
+        const int e2 = e + 2 - static_cast<int>(pr.k);       // dE = 8 - 4k
+        const int m2 = m + 1 - 2 * static_cast<int>(pr.bc);  // dM = -2 s
         bool in;
         if constexpr (SPLIT == 0) in = e2 >= lo && e2 <= hi;
         else if constexpr (SPLIT == 1) in = m2 >= lo && m2 <= hi;
@@ -402,48 +435,60 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
         const uint32_t idx2 = in ? table_index<BAND>(d, e2, m2) : cur;
         int64_t lng2 = tab[idx2];
         float uf = uniform_f(uw);
-        if constexpr (!std::is_same_v<std::decay_t<decltype(q)>, NoRounds>) philox_rounds<5>(q);
+        if constexpr (!std::is_same_v<std::decay_t<decltype(q)>, NoRounds>) {
+            philox_rounds<5>(q);
+            if (from_q) swn = q.c0;
+        }
+        Prop nx{};
+        if (more) nx = propose(swn);
         pin(q, lng2, uf);
+        pin_prop(nx.k, nx.bc);
         if (in && accept_pre((lng_cur & HI) - (lng2 & HI), uw, uf, K + PS)) {
             tab[cur] = lng_cur;
-            lds[(r << wsh) + lane] = row ^ (static_cast<RowT>(1) << c);
+            xor_bit(&lds[(pr.r << wsh) + lane], pr.c);
             e = e2;
             m = m2;
             cur = idx2;
             lng_cur = lng2;
+            const int f = pr.s0;
+            if (more && (f == nx.s0 || f == nx.s1 || f == nx.s2 || f == nx.s3 || f == nx.s4)) nx = propose(swn);
         }
         nseen += (lng_cur == 0) ? 1u : 0u;
         lng_cur += inc;
         if constexpr (PACKED) ovf = ovf || lng_cur < 0;
         ++t;
+        pr = nx;
     };
 
+    // trial t uses words (x, y) of Philox block t/2 when t is even, (z, w) when odd
     int64_t i = 0;
-    Words4 blk = {0, 0, 0, 0};
     NoRounds none;
-    if (n_trials > 0 && (t & 1)) {  // odd start: second half of the current block
+    Words4 blk = {0, 0, 0, 0};
+    Prop pr{};
+    if (n_trials > 0) {
         const uint64_t b = static_cast<uint64_t>(t) >> 1;
         blk = philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid, TAG_WL << 24);
-        trial(blk.z, blk.w, none);
-        ++i;
+        pr = propose((t & 1) ? blk.z : blk.x);
     }
-    if (i + 2 <= n_trials) {
-        const uint64_t b = static_cast<uint64_t>(t) >> 1;
-        blk = philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid, TAG_WL << 24);
+    if (n_trials > 0 && (t & 1)) {  // odd start: second half of the current block
+        const bool more = n_trials > 1;
+        const uint64_t b = (static_cast<uint64_t>(t) >> 1) + 1;
+        const Words4 nb = more ? philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid,
+                                               TAG_WL << 24)
+                               : Words4{0, 0, 0, 0};
+        trial(pr, blk.w, nb.x, more, false, none);
+        blk = nb;
+        ++i;
     }
     for (; i + 2 <= n_trials; i += 2) {
         // t is even here; blk is block t/2; the next block is computed in two
         // halves, each under the table gather of one of this pair of trials
         PhiloxRun q = philox_start(seed, (static_cast<uint64_t>(t) >> 1) + 1, gid);
-        trial(blk.x, blk.y, q);
-        trial(blk.z, blk.w, q);
+        trial(pr, blk.y, blk.z, true, false, q);
+        trial(pr, blk.w, 0u, i + 2 < n_trials, true, q);
         blk = {q.c0, q.c1, q.c2, q.c3};
     }
-    if (i < n_trials) {  // one trial left, t even: first half of block t/2
-        const uint64_t b = static_cast<uint64_t>(t) >> 1;
-        blk = philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid, TAG_WL << 24);
-        trial(blk.x, blk.y, none);
-    }
+    if (i < n_trials) trial(pr, blk.y, 0u, false, false, none);  // one trial left, t even
     tab[cur] = lng_cur;
     if (PACKED && ovf) atomicOr(&S.counters[1], ERR_PACK);
     S.e[g] = e;

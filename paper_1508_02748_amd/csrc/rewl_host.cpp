@@ -1117,10 +1117,13 @@ extern "C" rewl_status rewl_sweep_times(rewl_plan* P, float* ms, int32_t cap, in
 // header): runs k_accept_check synchronously on the current device and
 // returns the disagreement, exact-path and acceptance counts, plus the first
 // n_samp pairs and decisions (host arrays, nullable when n_samp = 0).
+// packed = 1 checks the form the sweep uses for packed table words (delta in
+// units of 2^-(K + 26), K <= 24).
 extern "C" rewl_status rewl_selfcheck_accept(int32_t K, uint64_t seed, int64_t n, double rel, int64_t* counts_out,
                                              int64_t* samp_delta, uint32_t* samp_u, int32_t* samp_dec,
-                                             int32_t n_samp) {
-    if (K < 6 || K > 40 || n < 0 || n_samp < 0 || n_samp > n || !counts_out || !(rel >= 0.0))
+                                             int32_t n_samp, int32_t packed) {
+    if (K < 6 || K > (packed ? MAX_K_PACKED : 40) || n < 0 || n_samp < 0 || n_samp > n || !counts_out ||
+        !(rel >= 0.0) || (packed != 0 && packed != 1))
         return fail(REWL_EINVAL, "bad self-check arguments");
     if (n_samp > 0 && (!samp_delta || !samp_u || !samp_dec)) return fail(REWL_EINVAL, "null sample arrays");
     void* d = nullptr;
@@ -1135,7 +1138,7 @@ extern "C" rewl_status rewl_selfcheck_accept(int32_t K, uint64_t seed, int64_t n
     auto* sdec = reinterpret_cast<int32_t*>(base + 32 + ns * 12);
     unsigned long long h[4] = {0, 0, 0, 0};
     e = hipMemcpy(cnt, h, 32, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_accept_check(K, seed, n, rel, cnt, sd, su, sdec, n_samp, nullptr);
+    if (e == hipSuccess) e = launch_accept_check(K, seed, n, rel, cnt, sd, su, sdec, n_samp, packed, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipMemcpy(h, cnt, 32, hipMemcpyDeviceToHost);
     if (e == hipSuccess && ns) e = hipMemcpy(samp_delta, sd, ns * 8, hipMemcpyDeviceToHost);

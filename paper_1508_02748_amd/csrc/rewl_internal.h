@@ -253,7 +253,7 @@ hipError_t launch_average(const DevState& S, hipStream_t st);
 hipError_t launch_snapshot(const DevState& S, hipStream_t st);
 hipError_t launch_exchange(const DevState& S, hipStream_t st);
 hipError_t launch_accept_check(int K, uint64_t seed, int64_t n, double rel, unsigned long long* counts, int64_t* sd,
-                               uint32_t* su, int32_t* sdec, int n_samp, hipStream_t st);
+                               uint32_t* su, int32_t* sdec, int n_samp, int packed, hipStream_t st);
 
 hipError_t launch_merge(const DevState& S, const MergeGeo& G, int max_nE, int norm, double* lng_out,
                         double* lnge_out, double* err_out, hipStream_t st);

@@ -257,34 +257,59 @@ __global__ void k_entry(DevState S, int64_t cap) {
 
 // ------------------------------------------------------------------ sweep
 // Acceptance decision identical to accept_move, reached faster: a single
-// precision estimate a of exp(x) (hardware exp2, relative error below 5e-6
-// for -23 < x < 0 including the rounding of x to float and the two roundings
-// of uf below) decides unless u lies within 1e-4 relative of a; only then is
-// the double-precision exp_neg evaluated, with u = (w + 1/2) 2^-32 formed
-// exactly in double.  Every path gives u < exp_neg(x) exactly.  The float
-// uniform uf = fl(fl(w) 2^-32 + 2^-33) (relative error below 2^-23) is formed
-// before the gathered ln g arrives, and the filter has no branches: only the
-// rare near-tie branches.
-__device__ __forceinline__ float uniform_f(uint32_t w) {
-    return __fmaf_rn(static_cast<float>(w), 0x1p-32f, 0x1p-33f);
+// precision estimate a of exp(x) (hardware exp2, relative error below 1e-5
+// for -23 < x < 0 including the roundings of x to float and of the uniform
+// below) decides unless u lies within about 1e-4 relative of a;
+// only then is the double-precision exp_neg evaluated, with u = (w + 1/2)
+// 2^-32 formed exactly in double.  Every path gives u < exp_neg(x) exactly.
+// The float uniform uf = fl(fl(w) 2^-32 + 2^-33) (relative error below
+// 2^-23) and its two scaled copies, uf / 0.9999 and uf / 1.0001 (one more
+// rounding each), are formed before the gathered ln g arrives, so that only
+// the exponential and two compares follow it; the filter has no branches:
+// only the rare near-tie branches.
+struct Uniform {
+    float acc_below;  // accept when a exceeds it: uf / 0.9999
+    float rej_above;  // reject when a is below it: uf / 1.0001
+};
+
+__device__ __forceinline__ Uniform uniform_f(uint32_t w) {
+    const float uf = __fmaf_rn(static_cast<float>(w), 0x1p-32f, 0x1p-33f);
+    return {uf * 1.00010001f, uf * 0.99990001f};
 }
 
-__device__ __forceinline__ bool accept_pre(int64_t delta, uint32_t w, float uf, int K, bool& exact_path) {
-    const double x = ldexp(static_cast<double>(delta), -K);
-    const float a = __builtin_amdgcn_exp2f(static_cast<float>(x) * 1.44269504f);
-    bool acc = delta >= 0 || uf < a * 0.9999f;
-    const bool rej = delta <= -(static_cast<int64_t>(23) << K) || uf > a * 1.0001f;
+//
+// LOW0: delta has its low 26 bits clear (packed table words, K >= 26).  Its
+// float value then comes from its two 32-bit halves with no double-precision
+// step: the low half has at most six significant bits and converts exactly,
+// the high half and the fused multiply-add round once each; the exact double
+// x is formed only on the near-tie path.
+template <bool LOW0 = false>
+__device__ __forceinline__ bool accept_pre(int64_t delta, uint32_t w, Uniform uf, int K, bool& exact_path) {
+    const bool inside = delta > -(static_cast<int64_t>(23) << K);
+    float x2;  // x log2(e)
+    if constexpr (LOW0) {
+        const float dh = static_cast<float>(static_cast<int32_t>(delta >> 32));
+        const float dl = static_cast<float>(static_cast<uint32_t>(delta));
+        x2 = __fmaf_rn(dh, 0x1p32f, dl) * ldexpf(1.44269504f, -K);
+    } else {
+        x2 = static_cast<float>(ldexp(static_cast<double>(delta), -K)) * 1.44269504f;
+    }
+    const float a = __builtin_amdgcn_exp2f(x2);
+    bool acc = delta >= 0 || (inside && uf.acc_below < a);
+    const bool rej = !inside || uf.rej_above > a;
     exact_path = !acc && !rej;
     if (exact_path) {
+        const double x = ldexp(static_cast<double>(delta), -K);
         const double u = __dmul_rn(__dadd_rn(static_cast<double>(w), 0.5), 1.0 / 4294967296.0);
         acc = u < exp_neg(x);
     }
     return acc;
 }
 
-__device__ __forceinline__ bool accept_pre(int64_t delta, uint32_t w, float uf, int K) {
+template <bool LOW0 = false>
+__device__ __forceinline__ bool accept_pre(int64_t delta, uint32_t w, Uniform uf, int K) {
     bool unused;
-    return accept_pre(delta, w, uf, K, unused);
+    return accept_pre<LOW0>(delta, w, uf, K, unused);
 }
 
 // First and second halves of a Philox4x32-10 evaluation, so that the next
@@ -322,18 +347,22 @@ struct NoRounds {};
 // the trial: the rounds computed before it overlap the table gather issued
 // before them (instead of being moved after the acceptance branch), and the
 // gather is waited for here on every path, not only inside the branch.
-__device__ __forceinline__ void pin(PhiloxRun& q, int64_t& v, float& f) {
-    asm volatile("" : "+v"(q.c0), "+v"(q.c1), "+v"(q.c2), "+v"(q.c3), "+v"(v), "+v"(f) : : "memory");
+__device__ __forceinline__ void pin(PhiloxRun& q, int64_t& v, Uniform& f) {
+    asm volatile("" : "+v"(q.c0), "+v"(q.c1), "+v"(q.c2), "+v"(q.c3), "+v"(v), "+v"(f.acc_below), "+v"(f.rej_above)
+                 : : "memory");
 }
 
-__device__ __forceinline__ void pin(NoRounds&, int64_t& v, float& f) {
-    asm volatile("" : "+v"(v), "+v"(f) : : "memory");
+__device__ __forceinline__ void pin(NoRounds&, int64_t& v, Uniform& f) {
+    asm volatile("" : "+v"(v), "+v"(f.acc_below), "+v"(f.rej_above) : : "memory");
 }
 
-// Pins the next trial's proposal at the same point, so that its LDS reads and
-// neighbour count are made while the gather is in flight.
-__device__ __forceinline__ void pin_prop(uint32_t& k, uint32_t& bc) {
-    asm volatile("" : "+v"(k), "+v"(bc));
+// Pins the next trial's targets at the same point, so that its proposal (LDS
+// reads, neighbour count) and both table addresses are made while the gather
+// is in flight.
+__device__ __forceinline__ void pin_next(uint32_t& a, uint32_t& b, bool& c) {
+    uint32_t ci = c ? 1u : 0u;
+    asm volatile("" : "+v"(a), "+v"(b), "+v"(ci));
+    c = ci != 0;
 }
 
 // Flips bit c of a walker's spin row in LDS in place (the row value a proposal
@@ -417,47 +446,72 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
         return pr;
     };
 
-    // One trial with the proposal `pr` (made from its site word before this
-    // trial began) and the uniform word uw.  While the table gather is in
-    // flight, `q` (a PhiloxRun) advances the next block by five rounds and the
-    // next trial's proposal is made from the spins as they are now (site word
-    // swn, or q.c0 after the rounds when from_q); a flip by this trial of one
-    // of the five sites that proposal read makes it again.  Flips are xors in
-    // LDS, so a row read before an earlier flip is never written back.
-    auto trial = [&](Prop& pr, uint32_t uw, uint32_t swn, bool more, bool from_q, auto& q) {
-        const int e2 = e + 2 - static_cast<int>(pr.k);       // dE = 8 - 4k
-        const int m2 = m + 1 - 2 * static_cast<int>(pr.bc);  // dM = -2 s
+    // Where a proposal leads from the state (ee, mm) with table entry ci: the
+    // trial bin, whether it lies in the window, and the table entry to gather
+    // (the current one when the proposal leaves the window).
+    struct Tgt {
+        int e2, m2;
         bool in;
-        if constexpr (SPLIT == 0) in = e2 >= lo && e2 <= hi;
-        else if constexpr (SPLIT == 1) in = m2 >= lo && m2 <= hi;
-        else in = e2 >= lo && e2 <= hi && m2 >= mlo && m2 <= mhi;
-        // gather unconditionally (the current bin when the proposal leaves the window)
-        const uint32_t idx2 = in ? table_index<BAND>(d, e2, m2) : cur;
-        int64_t lng2 = tab[idx2];
-        float uf = uniform_f(uw);
+        uint32_t idx;
+    };
+    auto target = [&](const Prop& pr, int ee, int mm, uint32_t ci) {
+        Tgt tg;
+        tg.e2 = ee + 2 - static_cast<int>(pr.k);       // dE = 8 - 4k
+        tg.m2 = mm + 1 - 2 * static_cast<int>(pr.bc);  // dM = -2 s
+        if constexpr (SPLIT == 0) tg.in = tg.e2 >= lo && tg.e2 <= hi;
+        else if constexpr (SPLIT == 1) tg.in = tg.m2 >= lo && tg.m2 <= hi;
+        else tg.in = tg.e2 >= lo && tg.e2 <= hi && tg.m2 >= mlo && tg.m2 <= mhi;
+        tg.idx = tg.in ? table_index<BAND>(d, tg.e2, tg.m2) : ci;
+        return tg;
+    };
+
+    // One trial with the proposal `pr` and its target `tg` (both made before
+    // this trial began) and the uniform word uw.  While the table gather is in
+    // flight, `q` (a PhiloxRun) advances the next block by five rounds, and the
+    // next trial's proposal is made from the spins as they are now (site word
+    // swn, or q.c0 after the rounds when from_q), with its target for either
+    // outcome of this trial.  A flip by this trial of one of the five sites
+    // that proposal read makes it again.  Flips are xors in LDS, so a row read
+    // before an earlier flip is never written back.
+    auto trial = [&](Prop& pr, Tgt& tg, uint32_t uw, uint32_t swn, bool more, bool from_q, auto& q) {
+        int64_t lng2 = tab[tg.idx];
+        const int64_t cur_hi = lng_cur & HI;
+        Uniform uf = uniform_f(uw);
         if constexpr (!std::is_same_v<std::decay_t<decltype(q)>, NoRounds>) {
             philox_rounds<5>(q);
             if (from_q) swn = q.c0;
         }
         Prop nx{};
-        if (more) nx = propose(swn);
+        Tgt ta{}, tr{};
+        bool touches = false;  // a flip by this trial would change what nx read
+        if (more) {
+            nx = propose(swn);
+            tr = target(nx, e, m, cur);
+            ta = target(nx, tg.e2, tg.m2, tg.idx);
+            const int f = pr.s0;
+            touches = f == nx.s0 || f == nx.s1 || f == nx.s2 || f == nx.s3 || f == nx.s4;
+        }
         pin(q, lng2, uf);
-        pin_prop(nx.k, nx.bc);
-        if (in && accept_pre((lng_cur & HI) - (lng2 & HI), uw, uf, K + PS)) {
+        pin_next(tr.idx, ta.idx, touches);
+        const bool acc = tg.in && accept_pre<PACKED>(cur_hi - (lng2 & HI), uw, uf, K + PS);
+        if (acc) {
             tab[cur] = lng_cur;
             xor_bit(&lds[(pr.r << wsh) + lane], pr.c);
-            e = e2;
-            m = m2;
-            cur = idx2;
+            e = tg.e2;
+            m = tg.m2;
+            cur = tg.idx;
             lng_cur = lng2;
-            const int f = pr.s0;
-            if (more && (f == nx.s0 || f == nx.s1 || f == nx.s2 || f == nx.s3 || f == nx.s4)) nx = propose(swn);
+            if (touches) {
+                nx = propose(swn);
+                ta = target(nx, e, m, cur);
+            }
         }
         nseen += (lng_cur == 0) ? 1u : 0u;
         lng_cur += inc;
         if constexpr (PACKED) ovf = ovf || lng_cur < 0;
         ++t;
         pr = nx;
+        tg = acc ? ta : tr;
     };
 
     // trial t uses words (x, y) of Philox block t/2 when t is even, (z, w) when odd
@@ -465,10 +519,12 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
     NoRounds none;
     Words4 blk = {0, 0, 0, 0};
     Prop pr{};
+    Tgt tg{};
     if (n_trials > 0) {
         const uint64_t b = static_cast<uint64_t>(t) >> 1;
         blk = philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid, TAG_WL << 24);
         pr = propose((t & 1) ? blk.z : blk.x);
+        tg = target(pr, e, m, cur);
     }
     if (n_trials > 0 && (t & 1)) {  // odd start: second half of the current block
         const bool more = n_trials > 1;
@@ -476,7 +532,7 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
         const Words4 nb = more ? philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid,
                                                TAG_WL << 24)
                                : Words4{0, 0, 0, 0};
-        trial(pr, blk.w, nb.x, more, false, none);
+        trial(pr, tg, blk.w, nb.x, more, false, none);
         blk = nb;
         ++i;
     }
@@ -484,11 +540,11 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
         // t is even here; blk is block t/2; the next block is computed in two
         // halves, each under the table gather of one of this pair of trials
         PhiloxRun q = philox_start(seed, (static_cast<uint64_t>(t) >> 1) + 1, gid);
-        trial(pr, blk.y, blk.z, true, false, q);
-        trial(pr, blk.w, 0u, i + 2 < n_trials, true, q);
+        trial(pr, tg, blk.y, blk.z, true, false, q);
+        trial(pr, tg, blk.w, 0u, i + 2 < n_trials, true, q);
         blk = {q.c0, q.c1, q.c2, q.c3};
     }
-    if (i < n_trials) trial(pr, blk.y, 0u, false, false, none);  // one trial left, t even
+    if (i < n_trials) trial(pr, tg, blk.y, 0u, false, false, none);  // one trial left, t even
     tab[cur] = lng_cur;
     if (PACKED && ovf) atomicOr(&S.counters[1], ERR_PACK);
     S.e[g] = e;
@@ -864,7 +920,7 @@ __global__ void __launch_bounds__(64) k_exchange(DevState S) {
 // pairs decided by the exact path, counts[2] += acceptances; the first n_samp
 // pairs and decisions are written out for a check against the CPU.
 __global__ void k_accept_check(int K, uint64_t seed, int64_t n, double rel, unsigned long long* counts,
-                               int64_t* sd, uint32_t* su, int32_t* sdec, int n_samp) {
+                               int64_t* sd, uint32_t* su, int32_t* sdec, int n_samp, int packed) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const Words4 b = philox4x32_10(seed, static_cast<uint32_t>(i), static_cast<uint32_t>(static_cast<uint64_t>(i) >> 32),
@@ -884,7 +940,10 @@ __global__ void k_accept_check(int K, uint64_t seed, int64_t n, double rel, unsi
     target = fmin(fmax(target, 0.0), 4294967295.0);
     const uint32_t w = static_cast<uint32_t>(target);
     bool exact_path = false;
-    const bool fast = accept_pre(delta, w, uniform_f(w), K, exact_path);
+    // packed: the sweep's form for packed table words, delta in units of 2^-(K + 26)
+    const bool fast = packed ? accept_pre<true>(delta * (static_cast<int64_t>(1) << PACK_SHIFT), w, uniform_f(w),
+                                                K + PACK_SHIFT, exact_path)
+                             : accept_pre(delta, w, uniform_f(w), K, exact_path);
     const bool spec = accept_move(delta, w, K);
     if (fast != spec) atomicAdd(&counts[0], 1ull);
     if (exact_path) atomicAdd(&counts[1], 1ull);
@@ -987,10 +1046,10 @@ hipError_t launch_snapshot(const DevState& S, hipStream_t st) {
 }
 
 hipError_t launch_accept_check(int K, uint64_t seed, int64_t n, double rel, unsigned long long* counts, int64_t* sd,
-                               uint32_t* su, int32_t* sdec, int n_samp, hipStream_t st) {
+                               uint32_t* su, int32_t* sdec, int n_samp, int packed, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_accept_check, dim3(blocks_for(n, 256)), dim3(256), 0, st, K, seed, n, rel, counts, sd, su,
-                       sdec, n_samp);
+                       sdec, n_samp, packed);
     return hipGetLastError();
 }
 

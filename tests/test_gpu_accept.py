@@ -26,21 +26,24 @@ def _selfcheck():
     import paper_1508_02748_amd as R
     f = R.lib().rewl_selfcheck_accept
     f.argtypes = [C.c_int32, C.c_uint64, C.c_int64, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                  C.c_int32]
+                  C.c_int32, C.c_int32]
     f.restype = C.c_int
     return R, f
 
 
-@pytest.mark.parametrize("K", [6, 20, 40])
-def test_float_filter_never_disagrees_with_the_fp64_comparison(K):
+@pytest.mark.parametrize("K,packed", [(6, 0), (20, 0), (40, 0), (6, 1), (20, 1), (24, 1)])
+def test_float_filter_never_disagrees_with_the_fp64_comparison(K, packed):
+    """packed = 1: the form used with packed table words, where the difference arrives in units
+    of 2^-(K + 26) with its low 26 bits clear and is converted to float from its two halves."""
     R, f = _selfcheck()
     n, ns = 10_000_000, 4000
     counts = np.zeros(3, np.int64)
     sd = np.zeros(ns, np.int64)
     su = np.zeros(ns, np.uint32)
     sdec = np.zeros(ns, np.int32)
-    print(f"case: acceptance self-check K={K}, {n} pairs", flush=True)
-    R._check(f(K, 1000 + K, n, 1e-3, counts.ctypes.data, sd.ctypes.data, su.ctypes.data, sdec.ctypes.data, ns))
+    print(f"case: acceptance self-check K={K}, packed={packed}, {n} pairs", flush=True)
+    R._check(f(K, 1000 + K + 77 * packed, n, 1e-3, counts.ctypes.data, sd.ctypes.data, su.ctypes.data,
+               sdec.ctypes.data, ns, packed))
     disagree, exact, acc = (int(x) for x in counts)
     assert disagree == 0, counts
     assert exact > n // 20, counts            # the exact path is really exercised

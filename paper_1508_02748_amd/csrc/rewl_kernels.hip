@@ -379,8 +379,12 @@ __device__ __forceinline__ void xor_bit(uint64_t* row, int c) {
 // window coordinate (0 energy, 1 magnetization, 2 both); LAYOUT bit 0: band
 // addressing of energy-window tables, bit 1: packed words (ln g in the high 38
 // bits; ln g differences then come from the words with their base bits
-// cleared, in units of 2^-(K + PACK_SHIFT)).
-template <typename RowT, int SPLIT, int LAYOUT>
+// cleared, in units of 2^-(K + PACK_SHIFT)).  AHEAD: each trial makes the next
+// trial's proposal and targets while its own gather is in flight (large
+// batches, where gathers often miss the L2); otherwise each trial makes its
+// own proposal first (small batches, whose gathers hit and leave nothing to
+// hide that work behind).  Both give the same trials.
+template <typename RowT, int SPLIT, int LAYOUT, bool AHEAD>
 __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int lane, int WG, int64_t g,
                                              int64_t n_trials) {
     constexpr int BAND = LAYOUT & 1;
@@ -416,6 +420,79 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
     int64_t lng_cur = tab[cur];
     bool ovf = false;  // packed words: ln g reached 2^37 units
 
+    if constexpr (!AHEAD) {
+    // One trial with the words (sw, uw) of its Philox block; `q` (a PhiloxRun)
+    // advances the next block by five rounds while the gather is in flight.
+    auto trial = [&](uint32_t sw, uint32_t uw, auto& q) {
+        int r, c;
+        site_rc(sw, L, r, c);
+        const int ru = r == 0 ? L - 1 : r - 1;
+        const int rd = r == L - 1 ? 0 : r + 1;
+        const int cl = c == 0 ? L - 1 : c - 1;
+        const int cr = c == L - 1 ? 0 : c + 1;
+        const RowT row = lds[(r << wsh) + lane];
+        const RowT rowu = lds[(ru << wsh) + lane];
+        const RowT rowd = lds[(rd << wsh) + lane];
+        const uint32_t bc = static_cast<uint32_t>(row >> c) & 1u;
+        // number of the four neighbours anti-aligned with the site
+        const uint32_t k = ((static_cast<uint32_t>(row >> cl) & 1u) ^ bc) +
+                           ((static_cast<uint32_t>(row >> cr) & 1u) ^ bc) +
+                           ((static_cast<uint32_t>(rowu >> c) & 1u) ^ bc) +
+                           ((static_cast<uint32_t>(rowd >> c) & 1u) ^ bc);
+        const int e2 = e + 2 - static_cast<int>(k);       // dE = 8 - 4k
+        const int m2 = m + 1 - 2 * static_cast<int>(bc);  // dM = -2 s
+        bool in;
+        if constexpr (SPLIT == 0) in = e2 >= lo && e2 <= hi;
+        else if constexpr (SPLIT == 1) in = m2 >= lo && m2 <= hi;
+        else in = e2 >= lo && e2 <= hi && m2 >= mlo && m2 <= mhi;
+        // gather unconditionally (the current bin when the proposal leaves the window)
+        const uint32_t idx2 = in ? table_index<BAND>(d, e2, m2) : cur;
+        int64_t lng2 = tab[idx2];
+        Uniform uf = uniform_f(uw);
+        const int64_t cur_hi = lng_cur & HI;
+        if constexpr (!std::is_same_v<std::decay_t<decltype(q)>, NoRounds>) philox_rounds<5>(q);
+        pin(q, lng2, uf);
+        if (in && accept_pre<PACKED>(cur_hi - (lng2 & HI), uw, uf, K + PS)) {
+            tab[cur] = lng_cur;
+            lds[(r << wsh) + lane] = row ^ (static_cast<RowT>(1) << c);
+            e = e2;
+            m = m2;
+            cur = idx2;
+            lng_cur = lng2;
+        }
+        nseen += (lng_cur == 0) ? 1u : 0u;
+        lng_cur += inc;
+        if constexpr (PACKED) ovf = ovf || lng_cur < 0;
+        ++t;
+    };
+
+    int64_t i = 0;
+    Words4 blk = {0, 0, 0, 0};
+    NoRounds none;
+    if (n_trials > 0 && (t & 1)) {  // odd start: second half of the current block
+        const uint64_t b = static_cast<uint64_t>(t) >> 1;
+        blk = philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid, TAG_WL << 24);
+        trial(blk.z, blk.w, none);
+        ++i;
+    }
+    if (i + 2 <= n_trials) {
+        const uint64_t b = static_cast<uint64_t>(t) >> 1;
+        blk = philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid, TAG_WL << 24);
+    }
+    for (; i + 2 <= n_trials; i += 2) {
+        // t is even here; blk is block t/2; the next block is computed in two
+        // halves, each under the table gather of one of this pair of trials
+        PhiloxRun q = philox_start(seed, (static_cast<uint64_t>(t) >> 1) + 1, gid);
+        trial(blk.x, blk.y, q);
+        trial(blk.z, blk.w, q);
+        blk = {q.c0, q.c1, q.c2, q.c3};
+    }
+    if (i < n_trials) {  // one trial left, t even: first half of block t/2
+        const uint64_t b = static_cast<uint64_t>(t) >> 1;
+        blk = philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid, TAG_WL << 24);
+        trial(blk.x, blk.y, none);
+    }
+    } else {
     // The proposal of a trial: its site, the site's spin and the number of its
     // four neighbours anti-aligned with it, and the linear indices of the five
     // sites it reads (for the check after a flip).
@@ -545,6 +622,7 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
         blk = {q.c0, q.c1, q.c2, q.c3};
     }
     if (i < n_trials) trial(pr, tg, blk.y, 0u, false, false, none);  // one trial left, t even
+    }
     tab[cur] = lng_cur;
     if (PACKED && ovf) atomicOr(&S.counters[1], ERR_PACK);
     S.e[g] = e;
@@ -567,7 +645,7 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
 // walkers in flight and so the set of table lines competing for the L2; the
 // tile-to-workgroup map is the same at every launch, so a walker stays on the
 // same XCD.
-template <typename RowT, int SPLIT, int LAYOUT>
+template <typename RowT, int SPLIT, int LAYOUT, bool AHEAD>
 __global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int64_t g_count,
                                                int64_t n_trials, int wpw) {
     extern __shared__ unsigned char lds_raw[];
@@ -581,7 +659,8 @@ __global__ void __launch_bounds__(256) k_sweep(DevState S, int64_t g_begin, int6
     const int64_t n_tiles = (g_count + per - 1) / per;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t gi = tile * per + wave * wpw + wl;
-        if (wl < wpw && gi < g_count) sweep_walker<RowT, SPLIT, LAYOUT>(S, lds, lane, WG, g_begin + gi, n_trials);
+        if (wl < wpw && gi < g_count)
+            sweep_walker<RowT, SPLIT, LAYOUT, AHEAD>(S, lds, lane, WG, g_begin + gi, n_trials);
     }
 }
 
@@ -979,19 +1058,24 @@ hipError_t launch_entry(const DevState& S, int64_t cap, hipStream_t st) {
 }
 
 // Instantiations: every split with dense addressing, energy windows also with
-// band addressing, each with unpacked and packed tables.
-#define REWL_SWEEP_KERNELS(RowT)                                                                          \
-    &k_sweep<RowT, 0, 0>, &k_sweep<RowT, 0, 1>, &k_sweep<RowT, 1, 0>, &k_sweep<RowT, 2, 0>,             \
-        &k_sweep<RowT, 0, 2>, &k_sweep<RowT, 0, 3>, &k_sweep<RowT, 1, 2>, &k_sweep<RowT, 2, 2>
+// band addressing, each with unpacked and packed tables, each in the direct
+// and the pipelined (AHEAD) form.
+#define REWL_SWEEP_KERNELS_A(RowT, A)                                                                     \
+    &k_sweep<RowT, 0, 0, A>, &k_sweep<RowT, 0, 1, A>, &k_sweep<RowT, 1, 0, A>, &k_sweep<RowT, 2, 0, A>, \
+        &k_sweep<RowT, 0, 2, A>, &k_sweep<RowT, 0, 3, A>, &k_sweep<RowT, 1, 2, A>, &k_sweep<RowT, 2, 2, A>
+#define REWL_SWEEP_KERNELS(RowT) REWL_SWEEP_KERNELS_A(RowT, false), REWL_SWEEP_KERNELS_A(RowT, true)
+
+// Launches of at least this many walkers use the pipelined trial.
+constexpr int64_t AHEAD_MIN_WALKERS = 16384;
 
 template <typename RowT>
 hipError_t launch_sweep_t(int split, int layout, dim3 grid, dim3 wg, size_t lds, hipStream_t st, const DevState& S,
                     int64_t g_begin, int64_t g_count, int64_t n_trials, int wpw) {
     using Kern = void (*)(DevState, int64_t, int64_t, int64_t, int);
-    static const Kern kerns[8] = {REWL_SWEEP_KERNELS(RowT)};
+    static const Kern kerns[16] = {REWL_SWEEP_KERNELS(RowT)};
     const int band = split == 0 && (layout & LAYOUT_BAND);
     const int base = split == 0 ? band : split + 1;  // 0..3: (0, dense) (0, band) (1) (2)
-    const Kern k = kerns[base + ((layout & LAYOUT_PACKED) ? 4 : 0)];
+    const Kern k = kerns[base + ((layout & LAYOUT_PACKED) ? 4 : 0) + (g_count >= AHEAD_MIN_WALKERS ? 8 : 0)];
     DevState s_arg = S;
     void* args[] = {&s_arg, &g_begin, &g_count, &n_trials, &wpw};
     return hipLaunchKernel(reinterpret_cast<const void*>(k), grid, wg, args, lds, st);
@@ -1014,7 +1098,7 @@ hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int
 
 hipError_t sweep_setup() {
     using Kern = void (*)(DevState, int64_t, int64_t, int64_t, int);
-    const Kern fns[16] = {REWL_SWEEP_KERNELS(uint32_t), REWL_SWEEP_KERNELS(uint64_t)};
+    const Kern fns[32] = {REWL_SWEEP_KERNELS(uint32_t), REWL_SWEEP_KERNELS(uint64_t)};
     for (Kern f : fns) {
         const hipError_t e =
             hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);

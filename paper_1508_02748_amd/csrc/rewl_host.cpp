@@ -296,10 +296,18 @@ int max_grid_of(const rewl_plan* P) {
     return static_cast<int>(std::max<long long>(1, lanes / wg_of(P)));
 }
 
+// The pipelined trial pays where gathers often miss the L2: many walkers (at
+// least 16,384, a quarter of the chip's lanes) whose tables are large (2^16 bins
+// per walker on average, 512 KB or more).  Small batches and small tables take
+// the direct trial; the plain form's launches (one window) always do.
+bool ahead_of(const rewl_plan* P) {
+    return P->n_walk >= 16384 && P->n_bins >= (static_cast<uint64_t>(P->n_walk) << 16);
+}
+
 rewl_status enqueue_sweep(rewl_plan* P, int64_t n, int ev_slot = -1) {
     if (ev_slot >= 0) HIPCHK(P, hipEventRecord(P->ev[2 * ev_slot], P->stream), "event record");
     HIPCHK(P, launch_sweep(P->S, 0, P->n_walk, n, P->l_max, wg_of(P), max_grid_of(P), P->tune.walkers_per_wave,
-                           P->split, P->layout, P->stream), "sweep launch");
+                           P->split, P->layout, ahead_of(P), P->stream), "sweep launch");
     if (ev_slot >= 0) HIPCHK(P, hipEventRecord(P->ev[2 * ev_slot + 1], P->stream), "event record");
     return REWL_OK;
 }
@@ -351,7 +359,7 @@ rewl_status run_interval_plain(rewl_plan* P) {
         const PDesc& q = P->pd[p];
         for (int w = 0; w < q.nwin; ++w) {
             HIPCHK(P, launch_sweep(P->S, q.walker_off + static_cast<int64_t>(w) * q.W, q.W, P->interval,
-                                   q.L, wg, 0, P->tune.walkers_per_wave, P->split, P->layout, P->stream),
+                                   q.L, wg, 0, P->tune.walkers_per_wave, P->split, P->layout, false, P->stream),
                    "plain sweep launch");
         }
     }
@@ -786,7 +794,7 @@ rewl_status rewl_sweep(rewl_plan* P, int64_t n) {
             for (const PDesc& q : P->pd)
                 for (int w = 0; w < q.nwin; ++w)
                     HIPCHK(P, launch_sweep(P->S, q.walker_off + static_cast<int64_t>(w) * q.W, q.W, m, q.L, wg, 0,
-                                           P->tune.walkers_per_wave, P->split, P->layout, P->stream),
+                                           P->tune.walkers_per_wave, P->split, P->layout, false, P->stream),
                            "plain sweep launch");
         } else if ((s = enqueue_sweep(P, m)) != REWL_OK) {
             return s;

@@ -244,8 +244,10 @@ rewl_status set_error(rewl_status st, const char* msg);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_init(const DevState& S, hipStream_t st);
 hipError_t launch_entry(const DevState& S, int64_t cap, hipStream_t st);
+// ahead: the pipelined trial (the next trial's proposal and targets made under
+// the current gather), for launches whose gathers often miss the L2.
 hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int64_t n_trials,
-                        int l_max, int wg, int max_grid, int wpw, int split, int layout, hipStream_t st);
+                        int l_max, int wg, int max_grid, int wpw, int split, int layout, bool ahead, hipStream_t st);
 hipError_t sweep_setup();
 hipError_t launch_flat(const DevState& S, hipStream_t st, int audit_only = 0);
 hipError_t launch_stage(const DevState& S, hipStream_t st);

@@ -1065,24 +1065,21 @@ hipError_t launch_entry(const DevState& S, int64_t cap, hipStream_t st) {
         &k_sweep<RowT, 0, 2, A>, &k_sweep<RowT, 0, 3, A>, &k_sweep<RowT, 1, 2, A>, &k_sweep<RowT, 2, 2, A>
 #define REWL_SWEEP_KERNELS(RowT) REWL_SWEEP_KERNELS_A(RowT, false), REWL_SWEEP_KERNELS_A(RowT, true)
 
-// Launches of at least this many walkers use the pipelined trial.
-constexpr int64_t AHEAD_MIN_WALKERS = 16384;
-
 template <typename RowT>
-hipError_t launch_sweep_t(int split, int layout, dim3 grid, dim3 wg, size_t lds, hipStream_t st, const DevState& S,
-                    int64_t g_begin, int64_t g_count, int64_t n_trials, int wpw) {
+hipError_t launch_sweep_t(int split, int layout, bool ahead, dim3 grid, dim3 wg, size_t lds, hipStream_t st,
+                          const DevState& S, int64_t g_begin, int64_t g_count, int64_t n_trials, int wpw) {
     using Kern = void (*)(DevState, int64_t, int64_t, int64_t, int);
     static const Kern kerns[16] = {REWL_SWEEP_KERNELS(RowT)};
     const int band = split == 0 && (layout & LAYOUT_BAND);
     const int base = split == 0 ? band : split + 1;  // 0..3: (0, dense) (0, band) (1) (2)
-    const Kern k = kerns[base + ((layout & LAYOUT_PACKED) ? 4 : 0) + (g_count >= AHEAD_MIN_WALKERS ? 8 : 0)];
+    const Kern k = kerns[base + ((layout & LAYOUT_PACKED) ? 4 : 0) + (ahead ? 8 : 0)];
     DevState s_arg = S;
     void* args[] = {&s_arg, &g_begin, &g_count, &n_trials, &wpw};
     return hipLaunchKernel(reinterpret_cast<const void*>(k), grid, wg, args, lds, st);
 }
 
 hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int64_t n_trials,
-                        int l_max, int wg, int max_grid, int wpw, int split, int layout, hipStream_t st) {
+                        int l_max, int wg, int max_grid, int wpw, int split, int layout, bool ahead, hipStream_t st) {
     if (g_count <= 0 || n_trials <= 0) return hipSuccess;
     if (wpw <= 0 || wpw > 64) wpw = 64;
     int grid = blocks_for(g_count, (wg / 64) * wpw);
@@ -1091,8 +1088,10 @@ hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int
     // band addressing applies to energy windows only (magnetization windows keep dense addressing)
     const hipError_t e =
         l_max <= 32
-            ? launch_sweep_t<uint32_t>(split, layout, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw)
-            : launch_sweep_t<uint64_t>(split, layout, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count, n_trials, wpw);
+            ? launch_sweep_t<uint32_t>(split, layout, ahead, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count,
+                                       n_trials, wpw)
+            : launch_sweep_t<uint64_t>(split, layout, ahead, dim3(grid), dim3(wg), lds, st, S, g_begin, g_count,
+                                       n_trials, wpw);
     return e != hipSuccess ? e : hipGetLastError();
 }
 

@@ -169,26 +169,33 @@ def test_packed_ln_g_guard_stops_where_the_oracle_reaches_2_37(form):
 @pytest.mark.parametrize("split,layout", [(0, 0), (0, 1), (0, 2), (0, 3), (1, 0), (1, 1), (1, 2), (1, 3), (2, 0),
                                           (2, 2)])
 def test_large_batches_every_split_and_layout(split, layout):
-    """Launches of 16,384 walkers or more take the pipelined trial (the next trial's proposal and
-    targets made under the current gather); smaller ones the direct trial, which every other
-    small test here covers.  A batch of small problems above that size, in every window split
-    and table layout and with both stage rules, against the oracle on sampled replicas."""
+    """A batched launch of 16,384 walkers or more whose tables average 2^16 bins per walker or more
+    takes the pipelined trial (the next trial's proposal and targets made under the current
+    gather); every other launch takes the direct trial, which the small tests here cover.  A
+    batch of 32 x 32 problems above both thresholds, in every window split and table layout, with
+    both stage rules and with a stage change at every boundary in half of them, against the
+    oracle on sampled replicas."""
     R = _R()
     if split == 2:
-        base = dict(L=8, n_windows=3, overlap=(1, 2), walkers_per_window=2, k_final=6, interval=1000, flat=(1, 2),
-                    split=2, m_windows=3, m_overlap=(1, 2))
+        base = dict(L=32, n_windows=4, overlap=(1, 2), walkers_per_window=8, k_final=8, interval=1000, split=2,
+                    m_windows=4, m_overlap=(1, 2))
     else:
-        base = dict(L=8, n_windows=5, overlap=(1, 2), walkers_per_window=3, k_final=6, interval=1000, flat=(1, 2),
-                    split=split)
-    per = R.Plan([R.Problem(seed=0, **base)], R.Tuning(table_layout=layout)).n_walkers
-    n = -(-17000 // per)
-    probs = [R.Problem(seed=s, stage_sync=R.SYNC_WINDOW if s % 2 else R.SYNC_PROBLEM, **base) for s in range(n)]
-    _say(f"case: split {split}, layout {layout}, {n} problems x {per} walkers, 40 intervals")
+        base = dict(L=32, n_windows=16, overlap=(3, 4), walkers_per_window=8, k_final=8, interval=1000, split=split)
+    one = R.Plan([R.Problem(seed=0, **base)], R.Tuning(table_layout=layout))
+    per, bins = one.n_walkers, one.sizes[0] // (8 if layout & 2 else 12)
+    one.close()
+    assert bins >= per << 16, (per, bins)
+    n = -(-16384 // per)
+    probs = [R.Problem(seed=s, stage_sync=R.SYNC_WINDOW if s % 2 else R.SYNC_PROBLEM,
+                       flat=(0, 1) if s % 4 < 2 else (4, 5), **base) for s in range(n)]
+    _say(f"case: split {split}, layout {layout}, {n} problems x {per} walkers (pipelined trial), 12 intervals")
     plan = R.Plan(probs, R.Tuning(table_layout=layout, graph_intervals=4))
     assert plan.n_walkers >= 16384
     plan.init()
-    plan.run(40)
-    for i in (0, 1, n // 2, n - 1):
+    plan.run(12)
+    for i in (0, 1, 2, n - 1):
         o = _oracle_of(probs[i])
-        o.run(40)
-        compare(plan, i, o)
+        o.run(12)
+        compare(plan, i, o, walkers=[0, 1, per // 2, per - 1])
+        compare(plan, i, o, tables=False)
+    plan.close()

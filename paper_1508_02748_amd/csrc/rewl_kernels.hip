@@ -283,9 +283,14 @@ __device__ __forceinline__ Uniform uniform_f(uint32_t w) {
 // step: the low half has at most six significant bits and converts exactly,
 // the high half and the fused multiply-add round once each; the exact double
 // x is formed only on the near-tie path.
+//
+// No range test: for x <= -23 the roundings of x move the estimate by less
+// than 1e-4 relative (x log2(e) > -150 before it flushes to zero), so it
+// stays below 1.03e-10, under the smallest rej_above, 0.9999 * 2^-33 =
+// 1.16e-10, and the trial is rejected; the exact path is reached only with
+// a >= rej_above, that is x > -22.9, inside the range of exp_neg.
 template <bool LOW0 = false>
 __device__ __forceinline__ bool accept_pre(int64_t delta, uint32_t w, Uniform uf, int K, bool& exact_path) {
-    const bool inside = delta > -(static_cast<int64_t>(23) << K);
     float x2;  // x log2(e)
     if constexpr (LOW0) {
         const float dh = static_cast<float>(static_cast<int32_t>(delta >> 32));
@@ -295,8 +300,8 @@ __device__ __forceinline__ bool accept_pre(int64_t delta, uint32_t w, Uniform uf
         x2 = static_cast<float>(ldexp(static_cast<double>(delta), -K)) * 1.44269504f;
     }
     const float a = __builtin_amdgcn_exp2f(x2);
-    bool acc = delta >= 0 || (inside && uf.acc_below < a);
-    const bool rej = !inside || uf.rej_above > a;
+    bool acc = delta >= 0 || uf.acc_below < a;
+    const bool rej = uf.rej_above > a;
     exact_path = !acc && !rej;
     if (exact_path) {
         const double x = ldexp(static_cast<double>(delta), -K);
@@ -372,6 +377,11 @@ __device__ __forceinline__ void xor_bit(uint64_t* row, int c) {
     atomicXor(reinterpret_cast<unsigned long long*>(row), 1ull << c);
 }
 
+// lo <= v <= hi (lo <= hi) as one unsigned compare.
+__device__ __forceinline__ bool in_range(int v, int lo, int hi) {
+    return static_cast<uint32_t>(v - lo) <= static_cast<uint32_t>(hi - lo);
+}
+
 // n_trials Wang-Landau trials (Eq. 1) for walker g (lane `lane` of a
 // workgroup of WG lanes).  Its spins sit in LDS column `lane`; no lane touches
 // another's data, so there are no barriers.  The bin the walker occupies is
@@ -418,7 +428,8 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
     uint32_t nseen = S.nseen[g];
     uint32_t cur = table_index<BAND>(d, e, m);
     int64_t lng_cur = tab[cur];
-    bool ovf = false;  // packed words: ln g reached 2^37 units
+    bool ovf = false;       // packed words: ln g reached 2^37 units
+    uint32_t ovf_hi = 0;    // the same, as the OR of the words' high halves (sign bit)
 
     if constexpr (!AHEAD) {
     // One trial with the words (sw, uw) of its Philox block; `q` (a PhiloxRun)
@@ -528,31 +539,42 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
     // (the current one when the proposal leaves the window).
     struct Tgt {
         int e2, m2;
-        bool in;
+        uint32_t in;  // 0 or 1 (a word, not a lane mask, so that selecting it is one instruction)
         uint32_t idx;
     };
     auto target = [&](const Prop& pr, int ee, int mm, uint32_t ci) {
         Tgt tg;
         tg.e2 = ee + 2 - static_cast<int>(pr.k);       // dE = 8 - 4k
         tg.m2 = mm + 1 - 2 * static_cast<int>(pr.bc);  // dM = -2 s
-        if constexpr (SPLIT == 0) tg.in = tg.e2 >= lo && tg.e2 <= hi;
-        else if constexpr (SPLIT == 1) tg.in = tg.m2 >= lo && tg.m2 <= hi;
-        else tg.in = tg.e2 >= lo && tg.e2 <= hi && tg.m2 >= mlo && tg.m2 <= mhi;
-        tg.idx = tg.in ? table_index<BAND>(d, tg.e2, tg.m2) : ci;
+        bool in;
+        if constexpr (SPLIT == 0) in = in_range(tg.e2, lo, hi);
+        else if constexpr (SPLIT == 1) in = in_range(tg.m2, lo, hi);
+        else in = in_range(tg.e2, lo, hi) & in_range(tg.m2, mlo, mhi);
+        tg.in = in ? 1u : 0u;
+        // the index is formed for every lane and then selected (an arithmetic
+        // result for a bin outside the window, never used as an address)
+        const uint32_t ti = table_index<BAND>(d, tg.e2, tg.m2);
+        tg.idx = in ? ti : ci;
         return tg;
     };
 
     // One trial with the proposal `pr` and its target `tg` (both made before
-    // this trial began) and the uniform word uw.  While the table gather is in
-    // flight, `q` (a PhiloxRun) advances the next block by five rounds, and the
-    // next trial's proposal is made from the spins as they are now (site word
-    // swn, or q.c0 after the rounds when from_q), with its target for either
-    // outcome of this trial.  A flip by this trial of one of the five sites
-    // that proposal read makes it again.  Flips are xors in LDS, so a row read
-    // before an earlier flip is never written back.
+    // this trial began, and the target's gather issued) and the uniform word
+    // uw.  While the gather is in flight, `q` (a PhiloxRun) advances the next
+    // block by five rounds, and the next trial's proposal is made from the
+    // spins as they are now (site word swn, or q.c0 after the rounds when
+    // from_q), with its target for either outcome of this trial.  Right after
+    // the decision the next target's gather is issued (when `more`).  A flip by
+    // this trial of one of the five sites that proposal read makes it again,
+    // and gathers again.  Flips are xors in LDS, so a row read before an
+    // earlier flip is never written back.
+    int64_t lng_nx = 0;  // the gather of the next trial's target, issued by the trial before
     auto trial = [&](Prop& pr, Tgt& tg, uint32_t uw, uint32_t swn, bool more, bool from_q, auto& q) {
-        int64_t lng2 = tab[tg.idx];
+        int64_t lng2 = lng_nx;
         const int64_t cur_hi = lng_cur & HI;
+        // the 32-bit LDS word holding the proposed site's spin, and its bit
+        uint32_t* const xw = reinterpret_cast<uint32_t*>(&lds[(pr.r << wsh) + lane]) + (pr.c >> 5);
+        const uint32_t xb = 1u << (pr.c & 31);
         Uniform uf = uniform_f(uw);
         if constexpr (!std::is_same_v<std::decay_t<decltype(q)>, NoRounds>) {
             philox_rounds<5>(q);
@@ -568,42 +590,54 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
             const int f = pr.s0;
             touches = f == nx.s0 || f == nx.s1 || f == nx.s2 || f == nx.s3 || f == nx.s4;
         }
-        pin(q, lng2, uf);
         pin_next(tr.idx, ta.idx, touches);
-        const bool acc = tg.in && accept_pre<PACKED>(cur_hi - (lng2 & HI), uw, uf, K + PS);
-        if (acc) {
-            tab[cur] = lng_cur;
-            xor_bit(&lds[(pr.r << wsh) + lane], pr.c);
-            e = tg.e2;
-            m = tg.m2;
-            cur = tg.idx;
-            lng_cur = lng2;
-            if (touches) {
-                nx = propose(swn);
-                ta = target(nx, e, m, cur);
-            }
+        pin(q, lng2, uf);
+        // Every lane runs the filter (no branch on `in`): a lane whose proposal
+        // leaves the window gathered its own bin, whose stored ln g is at most
+        // the one it holds, so the filter accepts there at once and `in` rejects.
+        // Then nothing is branched on: the flip is an xor with a zero mask on a
+        // rejection, and the new state is selected.
+        const bool acc = accept_pre<PACKED>(cur_hi - (lng2 & HI), uw, uf, K + PS) & (tg.in != 0);
+        const bool redo = acc & touches;
+        const Tgt tg_old = tg;
+        tg = acc ? ta : tr;
+        // the bin left behind is written back before the next gather, which may read it
+        if (acc) tab[cur] = lng_cur;
+        if (more) lng_nx = tab[tg.idx];
+        atomicXor(xw, acc ? xb : 0u);
+        e = acc ? tg_old.e2 : e;
+        m = acc ? tg_old.m2 : m;
+        cur = acc ? tg_old.idx : cur;
+        lng_cur = acc ? lng2 : lng_cur;
+        if (redo) {
+            nx = propose(swn);
+            tg = target(nx, e, m, cur);
+            if (more) lng_nx = tab[tg.idx];
         }
         nseen += (lng_cur == 0) ? 1u : 0u;
         lng_cur += inc;
-        if constexpr (PACKED) ovf = ovf || lng_cur < 0;
+        if constexpr (PACKED) ovf_hi |= static_cast<uint32_t>(static_cast<uint64_t>(lng_cur) >> 32);
         ++t;
         pr = nx;
-        tg = acc ? ta : tr;
     };
 
     // trial t uses words (x, y) of Philox block t/2 when t is even, (z, w) when odd
-    int64_t i = 0;
     NoRounds none;
     Words4 blk = {0, 0, 0, 0};
     Prop pr{};
     Tgt tg{};
+    const bool odd = n_trials > 0 && (t & 1);
     if (n_trials > 0) {
         const uint64_t b = static_cast<uint64_t>(t) >> 1;
         blk = philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid, TAG_WL << 24);
         pr = propose((t & 1) ? blk.z : blk.x);
         tg = target(pr, e, m, cur);
+        lng_nx = tab[tg.idx];
     }
-    if (n_trials > 0 && (t & 1)) {  // odd start: second half of the current block
+    // The load of the first bin's ln g completes here, so that the trial loop
+    // never waits on it (it would otherwise wait on every gather in flight).
+    asm volatile("" : "+v"(lng_cur));
+    if (odd) {  // odd start: second half of the current block
         const bool more = n_trials > 1;
         const uint64_t b = (static_cast<uint64_t>(t) >> 1) + 1;
         const Words4 nb = more ? philox4x32_10(seed, static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), gid,
@@ -611,20 +645,27 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
                                : Words4{0, 0, 0, 0};
         trial(pr, tg, blk.w, nb.x, more, false, none);
         blk = nb;
-        ++i;
     }
-    for (; i + 2 <= n_trials; i += 2) {
-        // t is even here; blk is block t/2; the next block is computed in two
-        // halves, each under the table gather of one of this pair of trials
+    // t is even here and blk is block t/2.  A pair of trials computes the next
+    // block in two halves, one under each trial's gather.  The pairs run
+    // (n_trials - 1) / 2 times on every lane, whatever its parity, so that the
+    // loop is uniform across the wavefront; their second trial makes the next
+    // proposal even when no trial follows (it is then not used).  One pair or
+    // one trial is left.
+    auto pair = [&](bool more) {
         PhiloxRun q = philox_start(seed, (static_cast<uint64_t>(t) >> 1) + 1, gid);
         trial(pr, tg, blk.y, blk.z, true, false, q);
-        trial(pr, tg, blk.w, 0u, i + 2 < n_trials, true, q);
+        trial(pr, tg, blk.w, 0u, more, true, q);
         blk = {q.c0, q.c1, q.c2, q.c3};
-    }
-    if (i < n_trials) trial(pr, tg, blk.y, 0u, false, false, none);  // one trial left, t even
+    };
+    const int64_t npairs = n_trials > 0 ? (n_trials - 1) >> 1 : 0;  // below 2^30 (at most 2^31 trials a launch)
+    for (int32_t j = 0; j < static_cast<int32_t>(npairs); ++j) pair(true);
+    const int64_t rem = n_trials - (odd ? 1 : 0) - 2 * npairs;  // 0, 1 or 2
+    if (rem == 2) pair(false);
+    else if (rem == 1) trial(pr, tg, blk.y, 0u, false, false, none);  // first half of block t/2
     }
     tab[cur] = lng_cur;
-    if (PACKED && ovf) atomicOr(&S.counters[1], ERR_PACK);
+    if (PACKED && (ovf || (ovf_hi >> 31) != 0)) atomicOr(&S.counters[1], ERR_PACK);
     S.e[g] = e;
     S.m[g] = m;
     S.t[g] = t;
@@ -1081,6 +1122,7 @@ hipError_t launch_sweep_t(int split, int layout, bool ahead, dim3 grid, dim3 wg,
 hipError_t launch_sweep(const DevState& S, int64_t g_begin, int64_t g_count, int64_t n_trials,
                         int l_max, int wg, int max_grid, int wpw, int split, int layout, bool ahead, hipStream_t st) {
     if (g_count <= 0 || n_trials <= 0) return hipSuccess;
+    if (n_trials > (static_cast<int64_t>(1) << 31)) return hipErrorInvalidValue;  // the pair loop counts in 32 bits
     if (wpw <= 0 || wpw > 64) wpw = 64;
     int grid = blocks_for(g_count, (wg / 64) * wpw);
     if (max_grid > 0 && grid > max_grid) grid = max_grid;

@@ -591,6 +591,12 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
             touches = f == nx.s0 || f == nx.s1 || f == nx.s2 || f == nx.s3 || f == nx.s4;
         }
         pin_next(tr.idx, ta.idx, touches);
+        // where the bin is written back on a move (a global pointer, so that
+        // the store stays a global store after the asm below)
+        __attribute__((address_space(1))) int64_t* cur_p =
+            (__attribute__((address_space(1))) int64_t*)(tab + cur);
+        uint32_t xbw = xb;
+        asm volatile("" : "+v"(cur_p), "+v"(xbw));
         pin(q, lng2, uf);
         // Every lane runs the filter (no branch on `in`): a lane whose proposal
         // leaves the window gathered its own bin, whose stored ln g is at most
@@ -600,15 +606,21 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
         const bool acc = accept_pre<PACKED>(cur_hi - (lng2 & HI), uw, uf, K + PS) & (tg.in != 0);
         const bool redo = acc & touches;
         const Tgt tg_old = tg;
-        tg = acc ? ta : tr;
         // the bin left behind is written back before the next gather, which may read it
-        if (acc) tab[cur] = lng_cur;
-        if (more) lng_nx = tab[tg.idx];
-        atomicXor(xw, acc ? xb : 0u);
-        e = acc ? tg_old.e2 : e;
-        m = acc ? tg_old.m2 : m;
-        cur = acc ? tg_old.idx : cur;
-        lng_cur = acc ? lng2 : lng_cur;
+        if (acc) *cur_p = lng_cur;
+        if (more) lng_nx = tab[acc ? ta.idx : tr.idx];
+        // the rest of the new state is selected after that gather is issued (the
+        // decision passes through an empty asm so that these selects are not
+        // moved into the branch above)
+        uint32_t accw = acc ? 1u : 0u;
+        asm volatile("" : "+v"(accw));
+        const bool acc2 = accw != 0;
+        tg = acc2 ? ta : tr;
+        atomicXor(xw, acc2 ? xbw : 0u);
+        e = acc2 ? tg_old.e2 : e;
+        m = acc2 ? tg_old.m2 : m;
+        cur = acc2 ? tg_old.idx : cur;
+        lng_cur = acc2 ? lng2 : lng_cur;
         if (redo) {
             nx = propose(swn);
             tg = target(nx, e, m, cur);

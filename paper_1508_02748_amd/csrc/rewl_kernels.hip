@@ -364,10 +364,8 @@ __device__ __forceinline__ void pin(NoRounds&, int64_t& v, Uniform& f) {
 // Pins the next trial's targets at the same point, so that its proposal (LDS
 // reads, neighbour count) and both table addresses are made while the gather
 // is in flight.
-__device__ __forceinline__ void pin_next(uint32_t& a, uint32_t& b, bool& c) {
-    uint32_t ci = c ? 1u : 0u;
-    asm volatile("" : "+v"(a), "+v"(b), "+v"(ci));
-    c = ci != 0;
+__device__ __forceinline__ void pin_next(uint32_t& a, uint32_t& b, uint32_t& c, uint32_t& d) {
+    asm volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
 }
 
 // Flips bit c of a walker's spin row in LDS in place (the row value a proposal
@@ -564,16 +562,19 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
     // block by five rounds, and the next trial's proposal is made from the
     // spins as they are now (site word swn, or q.c0 after the rounds when
     // from_q), with its target for either outcome of this trial.  Right after
-    // the decision the next target's gather is issued (when `more`).  A flip by
-    // this trial of one of the five sites that proposal read makes it again,
-    // and gathers again.  Flips are xors in LDS, so a row read before an
-    // earlier flip is never written back.
+    // the decision the next target's gather is issued (when `more`).  When this
+    // trial's flip is at one of the five sites that proposal read, the
+    // proposal for the accepted outcome is corrected arithmetically (the
+    // flipped spin is pr.bc before and 1 - pr.bc after): at its own site the
+    // spin and all four anti-alignments invert, at a neighbour that one
+    // anti-alignment does (the five sites are distinct for L >= 4).  Flips are
+    // xors in LDS, so a row read before an earlier flip is never written back.
     int64_t lng_nx = 0;  // the gather of the next trial's target, issued by the trial before
     auto trial = [&](Prop& pr, Tgt& tg, uint32_t uw, uint32_t swn, bool more, bool from_q, auto& q) {
         int64_t lng2 = lng_nx;
         const int64_t cur_hi = lng_cur & HI;
-        // the 32-bit LDS word holding the proposed site's spin, and its bit
-        uint32_t* const xw = reinterpret_cast<uint32_t*>(&lds[(pr.r << wsh) + lane]) + (pr.c >> 5);
+        // the 32-bit LDS word holding the proposed site's spin (its byte offset), and its bit
+        uint32_t xoff = static_cast<uint32_t>(((pr.r << wsh) + lane) * sizeof(RowT)) + ((pr.c >> 5) << 2);
         const uint32_t xb = 1u << (pr.c & 31);
         Uniform uf = uniform_f(uw);
         if constexpr (!std::is_same_v<std::decay_t<decltype(q)>, NoRounds>) {
@@ -582,21 +583,31 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
         }
         Prop nx{};
         Tgt ta{}, tr{};
-        bool touches = false;  // a flip by this trial would change what nx read
+        uint32_t bca = 0, ka = 0;  // nx's spin and neighbour count after this trial's flip
         if (more) {
             nx = propose(swn);
             tr = target(nx, e, m, cur);
-            ta = target(nx, tg.e2, tg.m2, tg.idx);
             const int f = pr.s0;
-            touches = f == nx.s0 || f == nx.s1 || f == nx.s2 || f == nx.s3 || f == nx.s4;
+            const uint32_t same = f == nx.s0 ? 1u : 0u;
+            const uint32_t nbr = ((f == nx.s1) | (f == nx.s2) | (f == nx.s3) | (f == nx.s4)) ? 1u : 0u;
+            bca = nx.bc ^ same;
+            // k + same (4 - 2k) + nbr (1 - 2 (pr.bc ^ nx.bc)), same and nbr exclusive
+            ka = nx.k + (same ? 4u - 2u * nx.k : 0u) + (nbr ? 1u - 2u * (pr.bc ^ nx.bc) : 0u);
+            Prop nxa = nx;
+            nxa.bc = bca;
+            nxa.k = ka;
+            ta = target(nxa, tg.e2, tg.m2, tg.idx);
         }
-        pin_next(tr.idx, ta.idx, touches);
-        // where the bin is written back on a move (a global pointer, so that
-        // the store stays a global store after the asm below)
-        __attribute__((address_space(1))) int64_t* cur_p =
-            (__attribute__((address_space(1))) int64_t*)(tab + cur);
+        pin_next(tr.idx, ta.idx, bca, ka);
+        // where the bin is written back on a move, and the next gather's
+        // address for either outcome (global pointers, so that the accesses stay
+        // global ones after the asm below)
+        using gptr = __attribute__((address_space(1))) int64_t*;
+        gptr cur_p = (gptr)(tab + cur);
+        gptr ta_p = (gptr)(tab + ta.idx);
+        gptr tr_p = (gptr)(tab + tr.idx);
         uint32_t xbw = xb;
-        asm volatile("" : "+v"(cur_p), "+v"(xbw));
+        asm volatile("" : "+v"(cur_p), "+v"(ta_p), "+v"(tr_p), "+v"(xbw), "+v"(xoff));
         pin(q, lng2, uf);
         // Every lane runs the filter (no branch on `in`): a lane whose proposal
         // leaves the window gathered its own bin, whose stored ln g is at most
@@ -604,28 +615,25 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
         // Then nothing is branched on: the flip is an xor with a zero mask on a
         // rejection, and the new state is selected.
         const bool acc = accept_pre<PACKED>(cur_hi - (lng2 & HI), uw, uf, K + PS) & (tg.in != 0);
-        const bool redo = acc & touches;
         const Tgt tg_old = tg;
         // the bin left behind is written back before the next gather, which may read it
         if (acc) *cur_p = lng_cur;
-        if (more) lng_nx = tab[acc ? ta.idx : tr.idx];
+        if (more) lng_nx = *(acc ? ta_p : tr_p);
         // the rest of the new state is selected after that gather is issued (the
-        // decision passes through an empty asm so that these selects are not
-        // moved into the branch above)
+        // decision and the flip's LDS offset pass through an empty asm, after the
+        // gather in program order, so that this work is not moved ahead of it)
         uint32_t accw = acc ? 1u : 0u;
-        asm volatile("" : "+v"(accw));
+        uint32_t xo = xoff;
+        asm volatile("" : "+v"(accw), "+v"(xo) : : "memory");
         const bool acc2 = accw != 0;
         tg = acc2 ? ta : tr;
-        atomicXor(xw, acc2 ? xbw : 0u);
+        atomicXor(reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(lds) + xo), acc2 ? xbw : 0u);
         e = acc2 ? tg_old.e2 : e;
         m = acc2 ? tg_old.m2 : m;
         cur = acc2 ? tg_old.idx : cur;
         lng_cur = acc2 ? lng2 : lng_cur;
-        if (redo) {
-            nx = propose(swn);
-            tg = target(nx, e, m, cur);
-            if (more) lng_nx = tab[tg.idx];
-        }
+        nx.bc = acc2 ? bca : nx.bc;
+        nx.k = acc2 ? ka : nx.k;
         nseen += (lng_cur == 0) ? 1u : 0u;
         lng_cur += inc;
         if constexpr (PACKED) ovf_hi |= static_cast<uint32_t>(static_cast<uint64_t>(lng_cur) >> 32);

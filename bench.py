@@ -129,10 +129,10 @@ VALU_PEAK_SLOTS = 256 * 64 * 2.4e9
 # device copy), by (workload, replicas, table layout, walkers per workgroup, grid waves per CU,
 # walkers per wavefront); measured on the current sweep kernel with rocprofv3 --pmc.  Other
 # shapes report null.
-TRAFFIC_BYTES = {("c4", 256, 3, 256, 4, 0): 136.81e9}
+TRAFFIC_BYTES = {("c4", 256, 3, 256, 4, 0): 137.60e9}
 # Share of the chip's VALU cycles the sweep keeps busy by the counters (4 x SQ_ACTIVE_INST_VALU
 # over 1024 SIMDs x GRBM_GUI_ACTIVE cycles per XCD), same keys; null where not measured.
-VALU_BUSY = {("c4", 256, 3, 256, 4, 0): 0.345}
+VALU_BUSY = {("c4", 256, 3, 256, 4, 0): 0.370}
 
 
 def launch_key(workload, replicas, layout, n_walk, wg, gw, wpw, n_cu=256):

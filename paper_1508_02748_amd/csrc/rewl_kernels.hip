@@ -361,18 +361,12 @@ __device__ __forceinline__ void pin(NoRounds&, int64_t& v, Uniform& f) {
     asm volatile("" : "+v"(v), "+v"(f.acc_below), "+v"(f.rej_above) : : "memory");
 }
 
-// Pins the next trial's targets at the same point, so that its proposal (LDS
-// reads, neighbour count) and both table addresses are made while the gather
-// is in flight.
+// Pins the next trial's targets (both table indices, and the accepted
+// outcome's corrected spin and neighbour count) at the same point, so that
+// its proposal (LDS reads, neighbour count) and both targets are made while
+// the gather is in flight.
 __device__ __forceinline__ void pin_next(uint32_t& a, uint32_t& b, uint32_t& c, uint32_t& d) {
     asm volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
-}
-
-// Flips bit c of a walker's spin row in LDS in place (the row value a proposal
-// read may be older than another flip in the same row).
-__device__ __forceinline__ void xor_bit(uint32_t* row, int c) { atomicXor(row, 1u << c); }
-__device__ __forceinline__ void xor_bit(uint64_t* row, int c) {
-    atomicXor(reinterpret_cast<unsigned long long*>(row), 1ull << c);
 }
 
 // lo <= v <= hi (lo <= hi) as one unsigned compare.
@@ -612,8 +606,8 @@ __device__ __forceinline__ void sweep_walker(const DevState& S, RowT* lds, int l
         // Every lane runs the filter (no branch on `in`): a lane whose proposal
         // leaves the window gathered its own bin, whose stored ln g is at most
         // the one it holds, so the filter accepts there at once and `in` rejects.
-        // Then nothing is branched on: the flip is an xor with a zero mask on a
-        // rejection, and the new state is selected.
+        // Only the write-back of the bin left is branched on: the flip is an xor
+        // with a zero mask on a rejection, and the new state is selected.
         const bool acc = accept_pre<PACKED>(cur_hi - (lng2 & HI), uw, uf, K + PS) & (tg.in != 0);
         const Tgt tg_old = tg;
         // the bin left behind is written back before the next gather, which may read it

@@ -199,3 +199,30 @@ def test_large_batches_every_split_and_layout(split, layout):
         compare(plan, i, o, walkers=[0, 1, per // 2, per - 1])
         compare(plan, i, o, tables=False)
     plan.close()
+
+
+def test_pipelined_trial_with_small_lattices():
+    """Small lattices in a batch that takes the pipelined trial: 16 replicas of the 64 x 64 problem
+    (large band tables) lift the batch's average above 2^16 bins per walker, so 1024 8 x 8 problems
+    in the same launches run the pipelined trial too.  At 8 x 8 the next proposal reads one of the
+    five sites an accepted flip changes in about one accepted trial in thirteen, so its arithmetic
+    correction (spin and anti-alignments inverted at the proposal's own site, one anti-alignment
+    at a neighbour) runs constantly.  The 8 x 8 problems, with both stage rules and with a stage
+    change at every boundary in half of them, against the oracle bit for bit."""
+    R = _R()
+    big = dict(L=64, n_windows=64, overlap=(3, 4), walkers_per_window=4, k_final=20, interval=1000)
+    small = dict(L=8, n_windows=3, overlap=(1, 2), walkers_per_window=4, k_final=8, interval=1000)
+    probs = [R.Problem(seed=s, **small, stage_sync=R.SYNC_WINDOW if s % 2 else R.SYNC_PROBLEM,
+                       flat=(0, 1) if s % 4 < 2 else (4, 5)) for s in range(1024)]
+    probs += [R.Problem(seed=5000 + s, **big) for s in range(16)]
+    _say("case: 1024 8x8 problems + 16 64x64 replicas, band packed (pipelined trial), 12 intervals")
+    plan = R.Plan(probs, R.Tuning(table_layout=R.LAYOUT_BAND_PACKED, graph_intervals=4))
+    bins = plan.sizes[0] // 8
+    assert plan.n_walkers >= 16384 and bins >= plan.n_walkers << 16, (plan.n_walkers, bins)
+    plan.init()
+    plan.run(12)
+    for i in (0, 1, 2, 3, 1023):
+        o = _oracle_of(probs[i])
+        o.run(12)
+        compare(plan, i, o)
+    plan.close()

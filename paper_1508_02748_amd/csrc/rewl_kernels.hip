@@ -1061,7 +1061,13 @@ __global__ void k_accept_check(int K, uint64_t seed, int64_t n, double rel, unsi
                                    0u, 5u << 24);
     const uint64_t span = static_cast<uint64_t>(23) << K;
     const uint64_t r64 = (static_cast<uint64_t>(b.x) << 32) | b.y;
-    const int64_t delta = -static_cast<int64_t>(r64 % span) - 1;
+    int64_t delta = -static_cast<int64_t>(r64 % span) - 1;
+    if ((i & 15) == 14) {
+        // far below the boundary (x <= -23, down to the largest ln g the layout holds: 2^37 units
+        // for packed words, 2^62 otherwise), where the filter decides with no range test
+        const uint64_t lim = static_cast<uint64_t>(1) << (packed ? 37 : 62);
+        delta = -static_cast<int64_t>(span + r64 % (lim - span));
+    }
     const double x = ldexp(static_cast<double>(delta), -K);
     const double ex = exp_neg(x) * 4294967296.0;
     double target;

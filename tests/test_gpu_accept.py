@@ -5,9 +5,11 @@ The sweep decides with a single-precision estimate of exp(x) and falls back to
 the FP64 exp_spec comparison only when u lies within 1e-4 of that estimate; its
 soundness rests on the float estimate's error bound.  The library's self-check
 kernel (not part of the public header) evaluates both decisions on 10^7 pairs
-(delta, u) per K, all within 1e-3 relative of the boundary and one in eight at
-the boundary word itself, and counts disagreements, which must be zero.  A
-sample of the pairs is also decided by the CPU oracle, which must agree.
+(delta, u) per K, within 1e-3 relative of the boundary and one in eight at the
+boundary word itself, and one in sixteen far below it (x <= -23, down to the
+largest ln g the layout holds), where the filter rejects with no range test;
+it counts disagreements, which must be zero.  A sample of the pairs is also
+decided by the CPU oracle, which must agree.
 """
 import ctypes as C
 

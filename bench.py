@@ -138,7 +138,10 @@ VALU_BUSY = {("c4", 256, 3, 256, 4, 0): 0.370}
 def launch_key(workload, replicas, layout, n_walk, wg, gw, wpw, n_cu=256):
     """Key of the measured tables above for this launch.  Shapes that differ only in `gw` are the
     same launch when both persistent grids give every tile of walkers its own workgroup (the cap
-    does not bind): such a shape shares the entry measured for the other."""
+    does not bind): such a shape shares the entry measured for the other.  None when the
+    walkers per workgroup are left to the library (no measured entry is claimed then)."""
+    if wg <= 0:
+        return None
     per = (wg // 64) * (wpw or 64)
     tiles = -(-n_walk // per)
 

@@ -27,3 +27,16 @@ def test_mixed_workload_problem_list():
     assert {p.interval for p in probs} == {10_000}
     # one-problem workloads keep seed = replica index
     assert [p.seed for p in bench.problems(4, R, bench.C2)] == [0, 1, 2, 3]
+
+
+def test_launch_key_of_measured_and_unknown_shapes():
+    """The traffic and VALU-busy tables are keyed by launch shape: grids that give every tile of
+    walkers its own workgroup are the same launch; a shape left to the library has no key."""
+    sys.path.insert(0, ROOT)
+    import bench
+    k = ("c4", 256, 3, 256, 4, 0)
+    assert k in bench.TRAFFIC_BYTES
+    assert bench.launch_key("c4", 256, 3, 65536, 256, 4, 0) == k
+    assert bench.launch_key("c4", 256, 3, 65536, 256, 8, 0) == k     # same launch: 256 tiles, 256 slots
+    assert bench.launch_key("c4", 256, 3, 65536, 256, 2, 0) not in bench.TRAFFIC_BYTES
+    assert bench.launch_key("c4", 256, 3, 65536, 0, 0, 0) is None      # --no-autotune, library's choice

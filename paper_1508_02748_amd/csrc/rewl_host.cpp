@@ -297,11 +297,12 @@ int max_grid_of(const rewl_plan* P) {
 }
 
 // The pipelined trial pays where gathers often miss the L2: many walkers (at
-// least 16,384, a quarter of the chip's lanes) whose tables are large (2^16 bins
-// per walker on average, 512 KB or more).  Small batches and small tables take
-// the direct trial; the plain form's launches (one window) always do.
+// least 16,384, a quarter of the chip's lanes) whose tables are not small (2^13
+// bins per walker on average, 64 KB or more packed: 16 x 16 windows and up).
+// Small batches and small tables take the direct trial; the plain form's
+// launches (one window) always do.
 bool ahead_of(const rewl_plan* P) {
-    return P->n_walk >= 16384 && P->n_bins >= (static_cast<uint64_t>(P->n_walk) << 16);
+    return P->n_walk >= 16384 && P->n_bins >= (static_cast<uint64_t>(P->n_walk) << 13);
 }
 
 rewl_status enqueue_sweep(rewl_plan* P, int64_t n, int ev_slot = -1) {

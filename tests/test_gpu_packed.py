@@ -169,7 +169,7 @@ def test_packed_ln_g_guard_stops_where_the_oracle_reaches_2_37(form):
 @pytest.mark.parametrize("split,layout", [(0, 0), (0, 1), (0, 2), (0, 3), (1, 0), (1, 1), (1, 2), (1, 3), (2, 0),
                                           (2, 2)])
 def test_large_batches_every_split_and_layout(split, layout):
-    """A batched launch of 16,384 walkers or more whose tables average 2^16 bins per walker or more
+    """A batched launch of 16,384 walkers or more whose tables average 2^13 bins per walker or more
     takes the pipelined trial (the next trial's proposal and targets made under the current
     gather); every other launch takes the direct trial, which the small tests here cover.  A
     batch of 32 x 32 problems above both thresholds, in every window split and table layout, with
@@ -184,7 +184,7 @@ def test_large_batches_every_split_and_layout(split, layout):
     one = R.Plan([R.Problem(seed=0, **base)], R.Tuning(table_layout=layout))
     per, bins = one.n_walkers, one.sizes[0] // (8 if layout & 2 else 12)
     one.close()
-    assert bins >= per << 16, (per, bins)
+    assert bins >= per << 13, (per, bins)
     n = -(-16384 // per)
     probs = [R.Problem(seed=s, stage_sync=R.SYNC_WINDOW if s % 2 else R.SYNC_PROBLEM,
                        flat=(0, 1) if s % 4 < 2 else (4, 5), **base) for s in range(n)]
@@ -203,7 +203,7 @@ def test_large_batches_every_split_and_layout(split, layout):
 
 def test_pipelined_trial_with_small_lattices():
     """Small lattices in a batch that takes the pipelined trial: 16 replicas of the 64 x 64 problem
-    (large band tables) lift the batch's average above 2^16 bins per walker, so 1024 8 x 8 problems
+    (large band tables) lift the batch's average above 2^13 bins per walker, so 1024 8 x 8 problems
     in the same launches run the pipelined trial too.  At 8 x 8 the next proposal reads one of the
     five sites an accepted flip changes in about one accepted trial in thirteen, so its arithmetic
     correction (spin and anti-alignments inverted at the proposal's own site, one anti-alignment
@@ -218,7 +218,7 @@ def test_pipelined_trial_with_small_lattices():
     _say("case: 1024 8x8 problems + 16 64x64 replicas, band packed (pipelined trial), 12 intervals")
     plan = R.Plan(probs, R.Tuning(table_layout=R.LAYOUT_BAND_PACKED, graph_intervals=4))
     bins = plan.sizes[0] // 8
-    assert plan.n_walkers >= 16384 and bins >= plan.n_walkers << 16, (plan.n_walkers, bins)
+    assert plan.n_walkers >= 16384 and bins >= plan.n_walkers << 13, (plan.n_walkers, bins)
     plan.init()
     plan.run(12)
     for i in (0, 1, 2, 3, 1023):

@@ -21,7 +21,7 @@ averaging its walkers, compared in accuracy and in trials to finish.
 Replica r uses seed r (the second group uses seed 1000 + r).  Progress is
 printed every minute.
 
-  python tests/long_convergence.py --config c2 --replicas 64 --seconds 780 --decompose --out gpurun_out/dec
+  python tests/long_convergence.py --config c2 --replicas 64 --seconds 780 --decompose --out runs/dec
 
 --decompose runs for the given time and then splits the error of the joined
 marginal ln g(E) at every energy, per replica, into (1) the error of the window

@@ -226,3 +226,25 @@ def test_pipelined_trial_with_small_lattices():
         o.run(12)
         compare(plan, i, o)
     plan.close()
+
+
+@pytest.mark.parametrize("wg,wpw", [(256, 32), (128, 17), (64, 64)])
+def test_pipelined_trial_launch_shapes(wg, wpw):
+    """The pipelined trial under other launch shapes (fewer walkers per wavefront, smaller
+    workgroups, a persistent grid smaller than the batch): a batch of 16 x 16 problems above both
+    thresholds gives the oracle's trajectories whatever the shape."""
+    R = _R()
+    base = dict(L=16, n_windows=8, overlap=(3, 4), walkers_per_window=4, k_final=10, interval=1000)
+    probs = [R.Problem(seed=300 + s, flat=(0, 1) if s % 2 else (4, 5), **base) for s in range(512)]
+    _say(f"case: 512 16x16 problems, walkers_per_wg {wg}, walkers_per_wave {wpw} (pipelined trial), 8 intervals")
+    plan = R.Plan(probs, R.Tuning(walkers_per_wg=wg, walkers_per_wave=wpw, grid_waves_per_cu=2,
+                                  graph_intervals=4))
+    bins = plan.sizes[0] // 12
+    assert plan.n_walkers >= 16384 and bins >= plan.n_walkers << 13, (plan.n_walkers, bins)
+    plan.init()
+    plan.run(8)
+    for i in (0, 1, 511):
+        o = _oracle_of(probs[i])
+        o.run(8)
+        compare(plan, i, o)
+    plan.close()

@@ -248,3 +248,28 @@ def test_pipelined_trial_launch_shapes(wg, wpw):
         o.run(8)
         compare(plan, i, o)
     plan.close()
+
+
+def test_pipelined_trial_odd_trial_counts():
+    """The pipelined trial with odd and tiny trial counts: a walker that starts on the second half
+    of a Philox block takes one trial first, the pair loop runs the same count on every lane, and
+    one pair or one trial is left; sweeps of 1, 2, 3, 333, 1000 and 7 trials with the boundary work
+    between them, on a 16 x 16 batch above both thresholds, against the oracle."""
+    R = _R()
+    base = dict(L=16, n_windows=8, overlap=(3, 4), walkers_per_window=4, k_final=10, interval=333)
+    probs = [R.Problem(seed=700 + s, **base) for s in range(512)]
+    _say("case: 512 16x16 problems, odd sweeps of the pipelined trial")
+    plan = R.Plan(probs)
+    bins = plan.sizes[0] // 12
+    assert plan.n_walkers >= 16384 and bins >= plan.n_walkers << 13, (plan.n_walkers, bins)
+    plan.init()
+    orcs = {i: _oracle_of(probs[i]) for i in (0, 511)}
+    for n in (1, 2, 3, 333, 1000, 7):
+        plan.sweep(n)
+        plan.reduce_lnf()
+        plan.exchange()
+        for i, o in orcs.items():
+            o.sweep(n)
+            o.boundary()
+            compare(plan, i, o)
+    plan.close()
